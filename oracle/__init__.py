@@ -1,0 +1,16 @@
+"""CPU oracle for exact k-mer matching (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+this package never imports the product library.
+"""
+from .oracle import (  # noqa: F401
+    build,
+    occurrences,
+    count,
+    transition_table,
+    automaton_scan,
+    pair_counts,
+    lib_path,
+    OracleLib,
+)
