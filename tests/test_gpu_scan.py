@@ -1,0 +1,152 @@
+"""GPU parity of the single-pattern scan (dfa_count through the C ABI) against the
+CPU oracle: counts and sorted positions must be bit-exact on every input.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08612_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1506_08612_amd import api  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_result(dtext, pat: bytes, t=None):
+    tab, m = api.device_table(pat)
+    c = api.count(dtext, tab, m, t=t)
+    c2, pos = api.positions(dtext, tab, m, t=t)
+    assert c2 == c
+    return c, pos.cpu().numpy()
+
+
+def check(text: np.ndarray, pat: bytes, t=None, dtext=None):
+    if dtext is None:
+        dtext = api.to_device(text)
+    want = oracle.occurrences(text, pat)
+    c, pos = gpu_result(dtext, pat, t)
+    assert c == want.size, (len(text), len(pat), c, want.size)
+    assert np.array_equal(pos, want)
+    return c
+
+
+def gc_text(n, seed, n_frac=0.03, plant=None, every=997):
+    t = synth.genome_like(n, seed, n_frac, n_run_mean=300)
+    if plant is not None and n >= len(plant):
+        for i in range(0, n - len(plant) + 1, every):
+            t[i:i + len(plant)] = np.frombuffer(plant, np.uint8)
+    return t
+
+
+def test_tiny_uniform_workload():
+    w = synth.tiny_uniform()
+    say("tiny uniform n=1MiB m=8")
+    c = check(w.text, w.patterns[0])
+    assert c >= 1
+    _, pos = gpu_result(api.to_device(w.text), w.patterns[0])
+    assert w.offsets[0] in pos.tolist()
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 17, 64, 255])
+def test_ragged_sizes(m):
+    rng = np.random.default_rng(m)
+    pat = synth.random_pattern(m, rng)
+    for n in [0, 1, 7, 15, 16, 17, 127, 128, 129, 255, 256, 1000, 4095, 4096, 4097, 65535,
+              65536 + 7, (1 << 20) + 13]:
+        say(f"ragged n={n} m={m}")
+        check(gc_text(n, n + m, plant=pat, every=331 + m), pat)
+
+
+TUNES = [
+    dict(chain_bytes=16), dict(chain_bytes=48), dict(chain_bytes=128), dict(chain_bytes=1024),
+    dict(chain_bytes=4096), dict(chain_bytes=65536),
+    dict(chains_per_lane=1), dict(chains_per_lane=2),
+    dict(waves_per_group=1), dict(waves_per_group=2, chains_per_lane=1),
+    dict(waves_per_group=3, chain_bytes=2000 // 16 * 16, chains_per_lane=2),
+]
+
+
+@pytest.mark.parametrize("tn", TUNES, ids=lambda d: ",".join(f"{k}={v}" for k, v in d.items()))
+def test_result_independent_of_launch_shape(tn):
+    text = gc_text(3_000_017, 99)
+    d = api.to_device(text)
+    rng = np.random.default_rng(7)
+    for m in (4, 8, 16, 32, 64, 200):
+        pat, _ = synth.drawn_pattern(text, m, rng)
+        say(f"tune {tn} m={m}")
+        check(text, pat, api.tune(**tn), dtext=d)
+
+
+def test_periodic_texts_dense_matches():
+    n = (1 << 20) + 3
+    text = np.full(n, ord("A"), np.uint8)
+    d = api.to_device(text)
+    for m in (1, 4, 64, 255):
+        say(f"A^n m={m}")
+        c, pos = gpu_result(d, b"A" * m)
+        assert c == n - m + 1
+        assert np.array_equal(pos, np.arange(n - m + 1))
+    k = 300_001
+    text = np.frombuffer(b"AC" * k, np.uint8).copy()
+    c, pos = gpu_result(api.to_device(text), b"ACA")
+    assert c == k - 1 and np.array_equal(pos, np.arange(0, 2 * k - 3, 2))
+
+
+def test_all_byte_values():
+    rng = np.random.default_rng(5)
+    text = rng.integers(0, 256, size=(1 << 19) + 77, dtype=np.uint8)
+    text[1000:1003] = [0, 255, 0]
+    text[5000:5003] = [0, 255, 0]
+    d = api.to_device(text)
+    for pat in (bytes([0, 255, 0]), bytes([0]), bytes([255]), text[40000:40002].tobytes()):
+        say(f"bytes pattern={list(pat)}")
+        check(text, pat, dtext=d)
+
+
+def test_positions_truncated_to_cap():
+    text = np.full(100_000, ord("G"), np.uint8)
+    d = api.to_device(text)
+    tab, m = api.device_table(b"GG")
+    c, pos = api.positions(d, tab, m, cap=1000)
+    assert c == 99_999
+    assert np.array_equal(pos.cpu().numpy(), np.arange(1000))
+
+
+def test_repeatable_bit_equal():
+    text = gc_text(5_000_000, 3)
+    d = api.to_device(text)
+    pat = text[123456:123464].tobytes()
+    a = gpu_result(d, pat)
+    b = gpu_result(d, pat)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.slow
+def test_paper_scale_genome():
+    """3.2 GB genome-like text (GC 41 %, 5 % 'N' runs of mean 50 kb), patterns of length
+    4..64 drawn from the text, scanned one per launch with the library's default launch
+    shape (the shape the benchmark times)."""
+    say("generating 3.2 GB genome-like text")
+    w = synth.paper_scale()
+    d = api.to_device(w.text)
+    for pat, off in zip(w.patterns, w.offsets):
+        say(f"paper scale m={len(pat)}")
+        want = oracle.occurrences(w.text, pat)
+        c, pos = gpu_result(d, pat)
+        assert c == want.size
+        assert np.array_equal(pos, want)
+        assert off in set(pos[max(0, np.searchsorted(pos, off) - 1):np.searchsorted(pos, off) + 1].tolist())
+    del d
+    torch.cuda.empty_cache()

@@ -1,0 +1,139 @@
+"""CPU tests of the library's host side: exported ABI, automaton build, argument
+checks, workspace sizing, and a CPU model of the scan's decomposition.
+
+No compute call reaches a GPU here: every dfa_count call below fails its
+argument checks, which run before anything is launched.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_08612_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "dfa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfa_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_header_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", api.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(dfa_\w+)", out))
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    # the binding wraps exactly what the header declares
+    assert sorted(api.exported_symbols()) == declared
+    for f in declared:
+        assert hasattr(api.lib, f)
+
+
+def test_version_and_error_string():
+    assert b"gfx950" in api.lib.dfa_version()
+    assert api.lib.dfa_table_bytes(0) == api.DFA_EINVAL
+    assert "m=0" in api.last_error()
+
+
+@pytest.mark.parametrize("alphabet", [b"AC", b"ACGT", b"ACGTN", bytes(range(256))])
+def test_build_matches_oracle_definition(alphabet):
+    rng = np.random.default_rng(len(alphabet))
+    a = np.frombuffer(alphabet, np.uint8)
+    for m in list(range(1, 20)) + [31, 32, 63, 64, 65, 100, 128, 200, 254, 255]:
+        p = a[rng.integers(0, a.size, m)].tobytes()
+        got = api.build_table(p)
+        want = oracle.transition_table(p)
+        assert np.array_equal(got, want), (m, p)
+
+
+def test_build_periodic_and_single():
+    for p in (b"A", b"AAAA", b"ACACA", b"ababaca", b"N" * 255, b"ACGT" * 16):
+        assert np.array_equal(api.build_table(p), oracle.transition_table(p)), p
+
+
+def test_table_bytes():
+    assert api.table_bytes(1) == 512
+    assert api.table_bytes(64) == 65 * 256
+    assert api.table_bytes(255) == 256 * 256
+    for bad in (0, -1, 256):
+        assert api.lib.dfa_table_bytes(bad) == api.DFA_EINVAL
+
+
+def test_build_rejects_bad_args():
+    buf = (ctypes.c_uint8 * 1024)()
+    pat = (ctypes.c_uint8 * 300)()
+    assert api.lib.dfa_build(None, 4, buf) == api.DFA_EINVAL
+    assert api.lib.dfa_build(pat, 4, None) == api.DFA_EINVAL
+    assert api.lib.dfa_build(pat, 0, buf) == api.DFA_EINVAL
+    assert api.lib.dfa_build(pat, 256, buf) == api.DFA_EINVAL
+
+
+def test_count_argument_checks_run_before_launch():
+    # bogus but non-null "device" pointers: the checks reject them before any HIP call
+    fake = 1 << 20
+    L = api.lib
+    assert L.dfa_count(fake, -1, fake, 8, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(fake, 10, fake, 0, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(fake, 10, fake, 256, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(None, 10, fake, 8, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(fake, 10, None, 8, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(fake, 10, fake, 8, None, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert L.dfa_count(fake + 1, 10, fake, 8, fake, None, 0, None, 0, None, None) == api.DFA_EINVAL
+    assert "aligned" in api.last_error()
+    assert L.dfa_count(fake, 10, fake, 8, fake, fake, -1, None, 0, None, None) == api.DFA_EINVAL
+    t = api.tune(chain_bytes=24)
+    assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    t = api.tune(chains_per_lane=3)
+    assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    t = api.tune()
+    t.reserved[1] = 5
+    assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    # positions requested with too small a workspace
+    assert L.dfa_count(fake, 1 << 20, fake, 8, fake, fake, 10, fake, 16, None, None) == api.DFA_ENOSPACE
+
+
+def test_workspace_bytes():
+    assert api.count_workspace_bytes(1 << 30, 8, False) == 0
+    a = api.count_workspace_bytes(1 << 30, 8, True)
+    b = api.count_workspace_bytes(1 << 30, 8, True, api.tune(chain_bytes=4096))
+    assert a > b > 0
+    assert api.count_workspace_bytes(0, 8, True) == 0
+    assert api.lib.dfa_count_workspace_bytes(-1, 8, 1, None) == api.DFA_EINVAL
+
+
+# ----------------------------------------------------------------------------------------
+# CPU model of the decomposition (Sec. III.A): walk g owns starts [gS, (g+1)S) and reads
+# m-1 bytes past them; summing what the walks report must give every match exactly once,
+# for every span length, including spans shorter than the pattern.
+# ----------------------------------------------------------------------------------------
+
+def model_scan(text: bytes, pat: bytes, S: int):
+    tab = oracle.transition_table(pat)
+    m, n = len(pat), len(text)
+    out = []
+    for start in range(0, n, S):
+        end = min(n, start + S + m - 1)
+        out.extend(start + p for p in oracle.automaton_scan(tab, text[start:end]).tolist())
+    return out
+
+
+@pytest.mark.parametrize("S", [1, 2, 3, 5, 16, 17, 64, 128, 1000])
+def test_decomposition_counts_every_match_once(S):
+    rng = np.random.default_rng(S)
+    for _ in range(30):
+        n = int(rng.integers(0, 1500))
+        t = np.frombuffer(b"AC", np.uint8)[rng.integers(0, 2, n)].tobytes()
+        m = int(rng.integers(1, 12))
+        p = np.frombuffer(b"AC", np.uint8)[rng.integers(0, 2, m)].tobytes()
+        assert model_scan(t, p, S) == oracle.occurrences(t, p).tolist()
