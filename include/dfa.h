@@ -51,11 +51,13 @@ extern "C" {
  * "choose for me".  Results never depend on these values, only speed does. */
 typedef struct dfa_tune {
     int64_t chain_bytes;     /* bytes of text one automaton walk owns (multiple of 16) */
-    int32_t waves_per_group; /* 64-lane waves per workgroup, 1..16 */
-    int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 or 2 */
+    int32_t waves_per_group; /* 64-lane waves per workgroup, 1..8 */
+    int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 (or 2 with
+                              * 64-byte rounds) */
     int32_t dfas_per_group;  /* batched scans: automata resident per workgroup, 1..64 */
     int32_t tile_bytes;      /* batched scans: text bytes per work item (multiple of 1024) */
-    int32_t reserved[4];     /* must be zero */
+    int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
+    int32_t reserved[3];     /* must be zero */
 } dfa_tune;
 
 /* Message for the last failed call on this thread ("" if none). */

@@ -37,7 +37,8 @@ class Tune(ctypes.Structure):
         ("chains_per_lane", ctypes.c_int32),
         ("dfas_per_group", ctypes.c_int32),
         ("tile_bytes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("line_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -82,8 +83,9 @@ def _check(rc: int) -> int:
 
 
 def tune(chain_bytes: int = 0, waves_per_group: int = 0, chains_per_lane: int = 0,
-         dfas_per_group: int = 0, tile_bytes: int = 0) -> Tune:
-    return Tune(chain_bytes, waves_per_group, chains_per_lane, dfas_per_group, tile_bytes)
+         dfas_per_group: int = 0, tile_bytes: int = 0, line_bytes: int = 0) -> Tune:
+    return Tune(chain_bytes, waves_per_group, chains_per_lane, dfas_per_group, tile_bytes,
+                line_bytes)
 
 
 def _tune_ptr(t: Optional[Tune]):

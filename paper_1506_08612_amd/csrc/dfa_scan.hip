@@ -40,29 +40,49 @@
 
 namespace {
 
-constexpr int kLine = 128;              // bytes of one walk fetched per round
-constexpr int kUnits = kLine / 16;      // 16-byte units per round
 constexpr int kRow = DFA_ALPHABET + 24;  // LDS bytes per table row
 constexpr int kWave = 64;
-constexpr int kXbufBytes = kWave * kLine;  // wave-private transpose buffer
 
 enum Mode { kCount = 0, kCountPerWalk = 1, kPositions = 2 };
 enum Guard { kNoGuard = 0, kWaveLimit = 1, kLaneLimit = 2 };
+
+// Geometry of one round: every walk receives LINE consecutive bytes (U units
+// of 16 bytes); one wave-wide 16-byte load covers 64/U walks.  The round is
+// transposed through a wave-private LDS buffer of 64 rows of LINE bytes per
+// walk slot, then walked one 16-byte unit at a time straight from LDS.
+template <int LINE>
+struct Geo {
+    static constexpr int U = LINE / 16;     // units per walk per round
+    static constexpr int kPer = kWave / U;  // walks per wave load
+    // XOR swizzle of the unit index by buffer row: any 8 consecutive lanes
+    // reading the same unit index hit 8 different 16-byte bank groups
+    __device__ static __forceinline__ int swz(int row) { return (row / (8 / U)) % U; }
+};
 
 struct ScanParams {
     const uint8_t *text;
     int64_t n;
     const uint8_t *table;
     int32_t m;
-    int32_t rounds;    // ceil((S + m - 1) / kLine)
+    int32_t rounds;    // ceil((S + m - 1) / LINE)
     int64_t S;         // span bytes per walk (multiple of 16)
     int64_t nwalks;
     unsigned long long *total;  // kCount / kCountPerWalk: += matches
     uint32_t *walk_count;       // kCountPerWalk: matches per walk
+    uint32_t *walk_buf;         // kCountPerWalk: end offsets (within the walk) of its first kBuffered matches
     const int64_t *walk_off;    // kPositions: output offset per walk
     int64_t *positions;         // kPositions
     int64_t cap;
 };
+
+// matches per walk whose positions the counting pass keeps; walks with more
+// are walked again by the positions pass
+constexpr int kBuffered = 2;
+
+// 16 text bytes as a native 4 x u32 register vector
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int table_lds_bytes(int m) { return ((m + 1) * kRow + 15) & ~15; }
 
 // Orders this lane's LDS accesses against the other lanes' of the same wave:
 // LDS executes one wave's instructions in order, so waiting for the lane's
@@ -78,91 +98,137 @@ __device__ __forceinline__ uint32_t table_step(uint32_t q, uint32_t c) {
     return *reinterpret_cast<lds_u8 *>(uintptr_t(__umul24(q, uint32_t(kRow)) + c));
 }
 
-__device__ __forceinline__ uint32_t word_of(const uint4 &v, int w) {
-    return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+__device__ __forceinline__ uint32_t word_of(const v4u &v, int w) { return v[w]; }
+
+// acc += number of lanes of the wave with `hit` set: one compare into a lane
+// mask, then a scalar bit count and add.  Written out so that the running
+// sum stays one scalar register (the compiler otherwise parks every step's
+// partial count in a register of its own).
+__device__ __forceinline__ void add_hits(uint32_t &acc, bool hit) {
+    const unsigned long long mask = __ballot(hit);
+    uint32_t tmp;
+    uint32_t a = __builtin_amdgcn_readfirstlane(acc);  // the count is wave-uniform
+    asm("s_bcnt1_i32_b64 %1, %2\n\ts_add_u32 %0, %0, %1" : "+s"(a), "=&s"(tmp) : "s"(mask) : "scc");
+    acc = a;
 }
 
 // 16 bytes at text[a..a+15]; bytes at or past n read as 0 (a byte outside
 // every pattern: it sends the automaton to q0 and never completes a match).
-__device__ __forceinline__ uint4 load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
-    if (a + 16 <= n) return *reinterpret_cast<const uint4 *>(text + a);
-    uint32_t w[4] = {0, 0, 0, 0};
+__device__ __forceinline__ v4u load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
+    if (a + 16 <= n) return *reinterpret_cast<const v4u *>(text + a);
+    v4u v = {0u, 0u, 0u, 0u};
+#pragma unroll
     for (int i = 0; i < 16; ++i)
-        if (a + i < n) w[i >> 2] |= uint32_t(text[a + i]) << (8 * (i & 3));
-    return make_uint4(w[0], w[1], w[2], w[3]);
+        if (a + i < n) v[i >> 2] |= uint32_t(text[a + i]) << (8 * (i & 3));
+    return v;
 }
 
-// Fetch round r of the wave's walks into registers: slot s, load j covers walk
-// 64*s + 8*j + (lane>>3), 16-byte unit (lane & 7).
-template <int K, bool GUARDED>
-__device__ __forceinline__ void fetch_round(uint4 (&pf)[K][kUnits], const ScanParams &p,
-                                            int64_t g0, int lane, int r) {
-    const int lrow = lane >> 3, lunit = lane & 7;
+// Fetch round r of the wave's walks into registers.  Slot s, load j covers the
+// walks 64*s + j*kPer + lane/U (unit lane % U of each): U lanes read one
+// LINE-byte piece, so every load is made of whole, aligned pieces.
+template <int K, int LINE, bool GUARDED>
+__device__ __forceinline__ void fetch_round(v4u (&pf)[K][Geo<LINE>::U], const ScanParams &p,
+                                            int64_t g0, uint32_t lane_off, int r) {
+    using G = Geo<LINE>;
 #pragma unroll
     for (int s = 0; s < K; ++s) {
 #pragma unroll
-        for (int j = 0; j < kUnits; ++j) {
-            const int64_t g = g0 + s * kWave + j * 8 + lrow;
-            const int64_t a = g * p.S + int64_t(r) * kLine + 16 * lunit;
+        for (int j = 0; j < G::U; ++j) {
+            // wave-uniform base of this load, plus a 32-bit per-lane offset
+            const int64_t gbase = g0 + s * kWave + j * G::kPer;
+            const uint8_t *base = p.text + gbase * p.S + int64_t(r) * LINE;
             if (GUARDED)
-                pf[s][j] = load_unit_guarded(p.text, p.n, a);
+                pf[s][j] = load_unit_guarded(p.text, p.n, (base - p.text) + int64_t(lane_off));
             else
-                pf[s][j] = *reinterpret_cast<const uint4 *>(p.text + a);
+                pf[s][j] = *reinterpret_cast<const v4u *>(base + lane_off);
         }
     }
 }
 
-// Registers -> LDS -> registers: afterwards t[s][u] holds bytes 16u..16u+15 of
-// this round for the lane's own walk in slot s.  Units are XOR-swizzled by
-// row so that both the writes and the transposed reads are bank-conflict free.
-template <int K>
-__device__ __forceinline__ void transpose_round(uint4 (&t)[K][kUnits], const uint4 (&pf)[K][kUnits],
-                                                uint4 *xb, int lane) {
-    const int lrow = lane >> 3, lunit = lane & 7;
+// Registers -> LDS: slot s of the wave's round lands in rows 64*s..64*s+63
+// of the wave's buffer, one row of LINE bytes per walk.
+template <int K, int LINE>
+__device__ __forceinline__ void stage_round(const v4u (&pf)[K][Geo<LINE>::U], v4u *xb, int lane) {
+    using G = Geo<LINE>;
+    const int lrow = lane / G::U, lunit = lane % G::U;
+    wave_lds_sync();  // the previous round's reads of this buffer are done
 #pragma unroll
     for (int s = 0; s < K; ++s) {
 #pragma unroll
-        for (int j = 0; j < kUnits; ++j) xb[(j * 8 + lrow) * kUnits + (lunit ^ lrow)] = pf[s][j];
-        wave_lds_sync();
-#pragma unroll
-        for (int u = 0; u < kUnits; ++u) t[s][u] = xb[lane * kUnits + (u ^ (lane & 7))];
-        wave_lds_sync();
+        for (int j = 0; j < G::U; ++j) {
+            const int row = j * G::kPer + lrow;
+            xb[(s * kWave + row) * G::U + (lunit ^ G::swz(row))] = pf[s][j];
+        }
     }
+    wave_lds_sync();
 }
 
-__host__ __device__ inline int table_lds_bytes(int m) { return ((m + 1) * kRow + 15) & ~15; }
+// Unit u (bytes 16u..16u+15 of the round) of the lane's own walk in slot s.
+template <int LINE>
+__device__ __forceinline__ v4u unit_of(const v4u *xb, int s, int lane, int u) {
+    using G = Geo<LINE>;
+    return xb[(s * kWave + lane) * G::U + (u ^ G::swz(lane))];
+}
 
-// Walk one 128-byte round.  G = kNoGuard: every byte counts; kWaveLimit: only
-// bytes j < wlim (same for the whole wave); kLaneLimit: only j < llim[s].
-template <int K, int MODE, int G>
-__device__ __forceinline__ void walk_round(const uint4 (&t)[K][kUnits], uint32_t (&q)[K],
-                                           const uint8_t *tab, uint32_t m, int wlim,
-                                           const int (&llim)[K], uint32_t &acc,
-                                           uint32_t (&cnt)[K], int64_t (&off)[K],
-                                           const int64_t (&pos0)[K], const ScanParams &p) {
+struct WalkLane {
+    int64_t wstart;  // first byte of the walk
+    uint32_t len;    // bytes the walk reads (span + m - 1, clipped at the text end)
+    uint32_t cnt;    // matches (per-walk counting pass)
+    uint32_t buf[kBuffered];
+    int64_t off;     // next output slot (positions pass)
+};
+
+// Walk 16 bytes: byte b of word w is byte jb + 4w + b of the walk.  GUARD:
+// only bytes below the walk's length count.  kCount: ballot + scalar count.
+// kCountPerWalk: the same, and when the wave's count moved (rare unless the
+// pattern is short) the unit is walked again from its start state to count
+// per walk and keep the first kBuffered match ends.  kPositions: write the
+// start offset of every match.
+template <int K, int MODE, bool GUARD>
+__device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
+                                          uint32_t &acc, WalkLane (&wl)[K], const ScanParams &p) {
+    uint32_t q0[K];
 #pragma unroll
-    for (int u = 0; u < kUnits; ++u) {
+    for (int s = 0; s < K; ++s) q0[s] = q[s];
+    const uint32_t acc0 = acc;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const uint32_t c = (t[s][w] >> (8 * b)) & 0xffu;
+                q[s] = table_step(q[s], c);
+                bool hit = q[s] == m;
+                if (GUARD) hit = hit && (jb + uint32_t(4 * w + b) < wl[s].len);
+                if (MODE != kPositions) {
+                    add_hits(acc, hit);
+                } else if (hit) {
+                    if (wl[s].off < p.cap) p.positions[wl[s].off] = wl[s].wstart + jb + (4 * w + b) - (m - 1);
+                    ++wl[s].off;
+                }
+            }
+        }
+    }
+    if (MODE == kCountPerWalk && acc != acc0) {
+#pragma unroll
+        for (int s = 0; s < K; ++s) q[s] = q0[s];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int j = u * 16 + w * 4 + b;
-                if (G == kWaveLimit && j >= wlim) continue;
 #pragma unroll
                 for (int s = 0; s < K; ++s) {
-                    const uint32_t c = (word_of(t[s][u], w) >> (8 * b)) & 0xffu;
+                    const uint32_t c = (t[s][w] >> (8 * b)) & 0xffu;
                     q[s] = table_step(q[s], c);
+                    const uint32_t j = jb + uint32_t(4 * w + b);
                     bool hit = q[s] == m;
-                    if (G == kLaneLimit) hit = hit && (j < llim[s]);
-                    if (MODE == kCount) {
-                        acc += __popcll(__ballot(hit));
-                    } else if (MODE == kCountPerWalk) {
-                        cnt[s] += hit ? 1u : 0u;
-                    } else {
-                        if (hit) {
-                            if (off[s] < p.cap) p.positions[off[s]] = pos0[s] + j - (m - 1);
-                            ++off[s];
-                        }
+                    if (GUARD) hit = hit && (j < wl[s].len);
+                    if (hit) {
+#pragma unroll
+                        for (int i = 0; i < kBuffered; ++i)
+                            if (wl[s].cnt == uint32_t(i)) wl[s].buf[i] = j;
+                        ++wl[s].cnt;
                     }
                 }
             }
@@ -170,32 +236,62 @@ __device__ __forceinline__ void walk_round(const uint4 (&t)[K][kUnits], uint32_t
     }
 }
 
-template <int K, int MODE>
-__global__ __launch_bounds__(256) void k_scan(ScanParams p) {
+// Walk one staged round: its units stream from LDS, the next one in flight
+// while the current one is walked.  `nbytes` (wave-uniform) bytes of the round
+// belong to every walk when GUARD is false; with GUARD, each walk's own length
+// decides.
+template <int K, int LINE, int MODE, bool GUARD>
+__device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q)[K], uint32_t m,
+                                           uint32_t rb, int nbytes, uint32_t &acc, WalkLane (&wl)[K],
+                                           const ScanParams &p) {
+    using G = Geo<LINE>;
+    const int units = GUARD ? G::U : (nbytes + 15) / 16;
+    v4u cur[K], nxt[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) cur[s] = unit_of<LINE>(xb, s, lane, 0);
+    for (int u = 0; u < units; ++u) {
+        if (u + 1 < units) {
+#pragma unroll
+            for (int s = 0; s < K; ++s) nxt[s] = unit_of<LINE>(xb, s, lane, u + 1);
+        }
+        const uint32_t jb = rb + uint32_t(16 * u);
+        if (GUARD || 16 * (u + 1) > nbytes)
+            walk_unit<K, MODE, true>(cur, q, m, jb, acc, wl, p);
+        else
+            walk_unit<K, MODE, false>(cur, q, m, jb, acc, wl, p);
+#pragma unroll
+        for (int s = 0; s < K; ++s) cur[s] = nxt[s];
+    }
+}
+
+template <int K, int LINE, int MODE>
+__global__ __launch_bounds__(512) void k_scan(ScanParams p) {
+    using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    // wave index, known to the compiler as uniform so that per-wave addresses
+    // live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const int nwaves = blockDim.x / kWave;
-    // table first (offset 0 keeps the step's address a single multiply-add),
-    // then one transpose buffer per wave
-    uint8_t *tab = smem;
-    uint4 *xb = reinterpret_cast<uint4 *>(smem + table_lds_bytes(p.m) + wave * kXbufBytes);
+    // table first (LDS address 0), then one transpose buffer per wave
+    v4u *xb = reinterpret_cast<v4u *>(smem + table_lds_bytes(p.m) + wave * (K * kWave * LINE));
 
     // table -> LDS, rows padded to kRow bytes
     {
         const uint32_t *tg = reinterpret_cast<const uint32_t *>(p.table);
         const int words = (p.m + 1) * (DFA_ALPHABET / 4);
         for (int i = threadIdx.x; i < words; i += blockDim.x)
-            *reinterpret_cast<uint32_t *>(tab + (i >> 6) * kRow + 4 * (i & 63)) = tg[i];
+            *reinterpret_cast<uint32_t *>(smem + (i >> 6) * kRow + 4 * (i & 63)) = tg[i];
     }
     __syncthreads();
 
     const int64_t g0 = (int64_t(blockIdx.x) * nwaves + wave) * (kWave * K);
     const uint32_t m = uint32_t(p.m);
+    const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(p.S) + 16u * uint32_t(lane % G::U);
 
     // per-lane walk bookkeeping
-    int64_t walk_len[K], pos0[K], off[K];
-    uint32_t q[K], cnt[K];
+    WalkLane wl[K];
+    uint32_t q[K];
     bool any_work = false;
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -206,57 +302,56 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
             len = p.n - start;
             if (len > p.S + p.m - 1) len = p.S + p.m - 1;
         }
-        walk_len[s] = len;
-        pos0[s] = start;
+        wl[s].wstart = start;
+        wl[s].len = uint32_t(len);
+        wl[s].cnt = 0;
+        wl[s].off = 0;
+#pragma unroll
+        for (int i = 0; i < kBuffered; ++i) wl[s].buf[i] = 0;
         q[s] = 0;
-        cnt[s] = 0;
-        off[s] = 0;
         if (MODE == kPositions) {
-            const bool has = g < p.nwalks && p.walk_count[g] != 0;
-            if (has) off[s] = p.walk_off[g];
+            // only walks whose matches did not all fit the counting pass's buffer
+            // (the other lanes walk along without writing: their offset is past
+            // any capacity)
+            const bool has = g < p.nwalks && p.walk_count[g] > uint32_t(kBuffered);
+            wl[s].off = has ? p.walk_off[g] : (int64_t(1) << 62);
             any_work |= has;
         }
     }
-    if (MODE == kPositions && __ballot(any_work) == 0) return;  // no match in this wave's spans
+    if (MODE == kPositions && __ballot(any_work) == 0) return;  // nothing left to write in this wave
 
     // whole wave in bounds: every load of every round lies inside the text
     const int64_t glast = g0 + kWave * K - 1;
-    const bool full = glast < p.nwalks && glast * p.S + int64_t(p.rounds) * kLine <= p.n;
-    const int lastlen = int(p.S + p.m - 1 - int64_t(p.rounds - 1) * kLine);  // bytes walked in the last round
-
-    uint4 pf[K][kUnits];
-    uint4 t[K][kUnits];
+    const bool full = glast < p.nwalks && glast * p.S + int64_t(p.rounds) * LINE <= p.n;
+    const int lastlen = int(p.S + p.m - 1 - int64_t(p.rounds - 1) * LINE);  // bytes walked in the last round
     uint32_t acc = 0;
-    int llim[K];
 
     if (full) {
-#pragma unroll
-        for (int s = 0; s < K; ++s) llim[s] = 0;
-        fetch_round<K, false>(pf, p, g0, lane, 0);
-        // every round but the last: all 128 bytes belong to the walk
-        for (int r = 0; r + 1 < p.rounds; ++r) {
-            transpose_round<K>(t, pf, xb, lane);
-            fetch_round<K, false>(pf, p, g0, lane, r + 1);
-            walk_round<K, MODE, kNoGuard>(t, q, tab, m, 0, llim, acc, cnt, off, pos0, p);
-#pragma unroll
-            for (int s = 0; s < K; ++s) pos0[s] += kLine;
+        // loads run two rounds ahead of the walk: pa holds even rounds, pb odd
+        // ones.  Fetches past the last round re-read the last round (an L2
+        // hit), so that both buffers are always written and stay in registers.
+        const int rlast = p.rounds - 1;
+        v4u pa[K][G::U], pb[K][G::U];
+        fetch_round<K, LINE, false>(pa, p, g0, lane_off, 0);
+        fetch_round<K, LINE, false>(pb, p, g0, lane_off, rlast < 1 ? rlast : 1);
+        for (int r = 0; r < p.rounds; r += 2) {
+            stage_round<K, LINE>(pa, xb, lane);
+            fetch_round<K, LINE, false>(pa, p, g0, lane_off, r + 2 < rlast ? r + 2 : rlast);
+            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
+                                             acc, wl, p);
+            if (r + 1 > rlast) break;
+            stage_round<K, LINE>(pb, xb, lane);
+            fetch_round<K, LINE, false>(pb, p, g0, lane_off, r + 3 < rlast ? r + 3 : rlast);
+            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
+                                             r + 1 == rlast ? lastlen : LINE, acc, wl, p);
         }
-        // last round: the walk ends after `lastlen` bytes
-        transpose_round<K>(t, pf, xb, lane);
-        walk_round<K, MODE, kWaveLimit>(t, q, tab, m, lastlen, llim, acc, cnt, off, pos0, p);
     } else {
-        fetch_round<K, true>(pf, p, g0, lane, 0);
+        v4u pf[K][G::U];
+        fetch_round<K, LINE, true>(pf, p, g0, lane_off, 0);
         for (int r = 0; r < p.rounds; ++r) {
-            transpose_round<K>(t, pf, xb, lane);
-            if (r + 1 < p.rounds) fetch_round<K, true>(pf, p, g0, lane, r + 1);
-#pragma unroll
-            for (int s = 0; s < K; ++s) {
-                const int64_t rem = walk_len[s] - int64_t(r) * kLine;
-                llim[s] = rem <= 0 ? 0 : (rem >= kLine ? kLine : int(rem));
-            }
-            walk_round<K, MODE, kLaneLimit>(t, q, tab, m, 0, llim, acc, cnt, off, pos0, p);
-#pragma unroll
-            for (int s = 0; s < K; ++s) pos0[s] += kLine;
+            stage_round<K, LINE>(pf, xb, lane);
+            if (r + 1 < p.rounds) fetch_round<K, LINE, true>(pf, p, g0, lane_off, r + 1);
+            walk_round<K, LINE, MODE, true>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
         }
     }
 
@@ -266,14 +361,16 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int64_t g = g0 + s * kWave + lane;
-            if (g < p.nwalks) p.walk_count[g] = cnt[s];
-            unsigned long long v = cnt[s];
-            // wave sum of the per-lane counts
-            for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
-            acc += uint32_t(v);
+            if (g < p.nwalks) {
+                p.walk_count[g] = wl[s].cnt;
+                if (wl[s].cnt != 0) {
+#pragma unroll
+                    for (int i = 0; i < kBuffered; ++i) p.walk_buf[g * kBuffered + i] = wl[s].buf[i];
+                }
+            }
         }
     }
-    // workgroup sum in LDS (reusing this wave's transpose buffer), one atomic
+    // workgroup sum in LDS (reusing the first transpose buffer), one atomic
     unsigned long long *red = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(p.m));
     __syncthreads();
     if (lane == 0) red[wave] = acc;
@@ -282,6 +379,21 @@ __global__ __launch_bounds__(256) void k_scan(ScanParams p) {
         unsigned long long sum = 0;
         for (int w = 0; w < nwaves; ++w) sum += red[w];
         if (sum) atomicAdd(p.total, sum);
+    }
+}
+
+// Positions of walks with 1..kBuffered matches, from the counting pass's
+// buffer: start = walk start + end offset - (m - 1).
+__global__ __launch_bounds__(256) void k_scatter_buffered(const uint32_t *walk_count, const uint32_t *walk_buf,
+                                                          const int64_t *walk_off, int64_t nwalks, int64_t S,
+                                                          int32_t m, int64_t *positions, int64_t cap) {
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < nwalks;
+         g += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t c = walk_count[g];
+        if (c == 0 || c > uint32_t(kBuffered)) continue;
+        const int64_t o = walk_off[g];
+        for (uint32_t i = 0; i < c; ++i)
+            if (o + i < cap) positions[o + i] = g * S + int64_t(walk_buf[g * kBuffered + i]) - (m - 1);
     }
 }
 
@@ -360,7 +472,8 @@ __global__ __launch_bounds__(kScanThreads) void k_walk_offsets(const uint32_t *c
 
 struct Plan {
     int64_t S = 0;
-    int K = 2;
+    int K = 1;
+    int line = 128;
     int wpg = 4;
     int rounds = 0;
     int64_t nwalks = 0;
@@ -368,68 +481,69 @@ struct Plan {
     size_t lds = 0;
 };
 
-template <int K, int MODE>
-const void *scan_fn() {
-    return reinterpret_cast<const void *>(&k_scan<K, MODE>);
+template <int K, int LINE>
+const void *scan_fn(int mode) {
+    if (mode == kCount) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCount>);
+    if (mode == kCountPerWalk) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWalk>);
+    return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions>);
 }
 
-const void *pick_scan(int K, int mode) {
-    if (K == 1) {
-        if (mode == kCount) return scan_fn<1, kCount>();
-        if (mode == kCountPerWalk) return scan_fn<1, kCountPerWalk>();
-        return scan_fn<1, kPositions>();
-    }
-    if (mode == kCount) return scan_fn<2, kCount>();
-    if (mode == kCountPerWalk) return scan_fn<2, kCountPerWalk>();
-    return scan_fn<2, kPositions>();
+// the (walks per lane, bytes per round) shapes compiled into the library
+const void *pick_scan(int K, int line, int mode) {
+    if (K == 1 && line == 128) return scan_fn<1, 128>(mode);
+    if (K == 1 && line == 64) return scan_fn<1, 64>(mode);
+    if (K == 2 && line == 64) return scan_fn<2, 64>(mode);
+    return nullptr;
 }
 
-size_t scan_lds_bytes(int wpg, int m) {
-    return size_t(wpg) * kXbufBytes + size_t(table_lds_bytes(m));
-}
-
-struct DevInfo {
-    int cus = 0;
-};
-
-int device_cus() {
-    static std::mutex mu;
-    static int cache[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    std::lock_guard<std::mutex> lk(mu);
-    if (!cache[dev]) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-        cache[dev] = v;
-    }
-    return cache[dev];
+size_t scan_lds_bytes(int wpg, int K, int line, int m) {
+    return size_t(wpg) * K * kWave * line + size_t(table_lds_bytes(m));
 }
 
 int64_t min_span(const dfa_tune *t) {
     return (t && t->chain_bytes > 0) ? t->chain_bytes : dfa::kMinChainBytes;
 }
 
+constexpr int kDefaultK = 1;
+constexpr int kDefaultLine = 128;
+constexpr int kDefaultWpg = 4;
+
+// Default span of one walk.  Many short walks (far more workgroups than fit
+// on the device at once) let the hardware dispatcher balance the load; the
+// span stays long against m so the overlap re-read (m-1 bytes) stays small.
+constexpr int64_t kSpanTarget = 2048;
+
 bool check_tune(const dfa_tune *t) {
     if (!t) return true;
-    if (t->chain_bytes < 0 || (t->chain_bytes % 16) != 0 || (t->chain_bytes > 0 && t->chain_bytes < 16)) {
+    if (t->chain_bytes < 0 || (t->chain_bytes % 16) != 0) {
         dfa::set_error("tune.chain_bytes=%lld must be a positive multiple of 16 (or 0)",
                        (long long)t->chain_bytes);
         return false;
     }
-    if (t->chain_bytes > (int64_t(1) << 30)) {
-        dfa::set_error("tune.chain_bytes=%lld too large", (long long)t->chain_bytes);
+    if (t->chain_bytes > (int64_t(1) << 24)) {
+        dfa::set_error("tune.chain_bytes=%lld above 2^24", (long long)t->chain_bytes);
         return false;
     }
-    if (t->waves_per_group < 0 || t->waves_per_group > 4) {
-        dfa::set_error("tune.waves_per_group=%d outside [1, 4]", t->waves_per_group);
+    if (t->waves_per_group < 0 || t->waves_per_group > 8) {
+        dfa::set_error("tune.waves_per_group=%d outside [1, 8]", t->waves_per_group);
         return false;
     }
-    if (t->chains_per_lane < 0 || t->chains_per_lane > 2) {
-        dfa::set_error("tune.chains_per_lane=%d outside [1, 2]", t->chains_per_lane);
+    if (t->line_bytes != 0 && t->line_bytes != 64 && t->line_bytes != 128) {
+        dfa::set_error("tune.line_bytes=%d must be 64 or 128 (or 0)", t->line_bytes);
         return false;
     }
-    for (int i = 0; i < 4; ++i)
+    const int line = t->line_bytes ? t->line_bytes : kDefaultLine;
+    const int K = t->chains_per_lane ? t->chains_per_lane : kDefaultK;
+    if (t->chains_per_lane < 0 || !pick_scan(K, line, kCount)) {
+        dfa::set_error("tune: chains_per_lane=%d with line_bytes=%d is not a built shape "
+                       "(1 with 64 or 128, 2 with 64)", t->chains_per_lane, line);
+        return false;
+    }
+    if (t->dfas_per_group < 0 || t->tile_bytes < 0) {
+        dfa::set_error("tune: negative field");
+        return false;
+    }
+    for (int i = 0; i < 3; ++i)
         if (t->reserved[i]) {
             dfa::set_error("tune.reserved must be zero");
             return false;
@@ -441,36 +555,39 @@ bool check_tune(const dfa_tune *t) {
 // the workspace without a device query.
 int64_t max_walks(int64_t n, const dfa_tune *t) { return n > 0 ? dfa::ceil_div(n, min_span(t)) : 0; }
 
-int64_t workspace_for(int64_t nw) {
-    if (nw <= 0) return 0;
+// workspace layout: walk counts u32[nw] | walk offsets i64[nw] | block
+// partials u64[nb] | buffered match ends u32[nw * kBuffered]
+struct WsLayout {
+    int64_t cnt = 0, off = 0, part = 0, buf = 0, total = 0;
+};
+WsLayout ws_layout(int64_t nw) {
+    WsLayout L;
+    if (nw <= 0) return L;
     const int64_t nb = dfa::ceil_div(nw, kScanBlock);
-    return dfa::round_up(nw * 4, 256) + dfa::round_up(nw * 8, 256) + dfa::round_up(nb * 8, 256);
+    L.cnt = 0;
+    L.off = L.cnt + dfa::round_up(nw * 4, 256);
+    L.part = L.off + dfa::round_up(nw * 8, 256);
+    L.buf = L.part + dfa::round_up(nb * 8, 256);
+    L.total = L.buf + dfa::round_up(nw * 4 * kBuffered, 256);
+    return L;
 }
+int64_t workspace_for(int64_t nw) { return ws_layout(nw).total; }
 
 bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
-    pl.K = (t && t->chains_per_lane) ? t->chains_per_lane : 2;
-    pl.wpg = (t && t->waves_per_group) ? t->waves_per_group : 4;
-    pl.lds = scan_lds_bytes(pl.wpg, m);
+    pl.K = (t && t->chains_per_lane) ? t->chains_per_lane : kDefaultK;
+    pl.line = (t && t->line_bytes) ? t->line_bytes : kDefaultLine;
+    pl.wpg = (t && t->waves_per_group) ? t->waves_per_group : kDefaultWpg;
+    pl.lds = scan_lds_bytes(pl.wpg, pl.K, pl.line, m);
     if (t && t->chain_bytes > 0) {
         pl.S = t->chain_bytes;
     } else {
-        // one resident wave per group of 64*K walks: size the spans so that the
-        // whole text is covered by the walks that fit on the device at once
-        int cus = device_cus();
-        if (cus <= 0) {
-            dfa::set_error("no HIP device");
-            return false;
-        }
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_scan(pl.K, mode), pl.wpg * kWave,
-                                                         pl.lds) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        const int64_t resident = int64_t(cus) * per_cu * pl.wpg * kWave * pl.K;
-        pl.S = dfa::round_up(dfa::ceil_div(n, resident), 16);
-        if (pl.S < dfa::kMinChainBytes) pl.S = dfa::kMinChainBytes;
+        // whole rounds: S + m - 1 fills R rounds up to less than 16 bytes
+        const int64_t halo = dfa::round_up(m - 1, 16);
+        int64_t R = dfa::ceil_div(kSpanTarget + m - 1, pl.line);
+        pl.S = R * pl.line - halo;
+        if (pl.S < dfa::kMinChainBytes) pl.S = dfa::round_up(dfa::kMinChainBytes, 16);
     }
-    pl.rounds = int(dfa::ceil_div(pl.S + m - 1, kLine));
+    pl.rounds = int(dfa::ceil_div(pl.S + m - 1, pl.line));
     pl.nwalks = n > 0 ? dfa::ceil_div(n, pl.S) : 0;
     const int64_t walks_per_block = int64_t(pl.wpg) * kWave * pl.K;
     pl.blocks = dfa::ceil_div(pl.nwalks, walks_per_block);
@@ -484,13 +601,17 @@ bool hip_ok(hipError_t e, const char *what) {
 }
 
 int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) {
-    const void *fn = pick_scan(pl.K, mode);
+    const void *fn = pick_scan(pl.K, pl.line, mode);
+    if (!fn) {
+        dfa::set_error("no kernel for K=%d line=%d", pl.K, pl.line);
+        return DFA_EINVAL;
+    }
     static std::mutex mu;
     {
         std::lock_guard<std::mutex> lk(mu);
         // allow the largest table (m = 255) with the largest workgroup
         if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(scan_lds_bytes(4, DFA_MAX_M))),
+                                        int(scan_lds_bytes(8, 1, 128, DFA_MAX_M))),
                     "hipFuncSetAttribute"))
             return DFA_EHIP;
     }
@@ -574,22 +695,29 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
         return rc;
     }
 
-    // workspace: per-walk counts | per-walk offsets | block partials
     uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
     const int64_t nw = pl.nwalks;
     const int64_t nb = dfa::ceil_div(nw, kScanBlock);
-    uint32_t *wcnt = reinterpret_cast<uint32_t *>(ws);
-    int64_t *woff = reinterpret_cast<int64_t *>(ws + dfa::round_up(nw * 4, 256));
-    unsigned long long *part =
-        reinterpret_cast<unsigned long long *>(ws + dfa::round_up(nw * 4, 256) + dfa::round_up(nw * 8, 256));
+    const WsLayout L = ws_layout(nw);
+    uint32_t *wcnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
+    int64_t *woff = reinterpret_cast<int64_t *>(ws + L.off);
+    unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + L.part);
+    uint32_t *wbuf = reinterpret_cast<uint32_t *>(ws + L.buf);
 
     sp.walk_count = wcnt;
+    sp.walk_buf = wbuf;
     int rc = launch_scan(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
     hipLaunchKernelGGL(k_walk_sums, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw, part);
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, st, part, nb, count);
     hipLaunchKernelGGL(k_walk_offsets, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw,
                        (const unsigned long long *)part, woff);
+    {
+        const int64_t want = dfa::ceil_div(nw, 256);
+        const unsigned grid = unsigned(want < 65536 ? want : 65536);
+        hipLaunchKernelGGL(k_scatter_buffered, dim3(grid), dim3(256), 0, st, (const uint32_t *)wcnt,
+                           (const uint32_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions, cap);
+    }
     if (!hip_ok(hipGetLastError(), "prefix-sum launch")) return DFA_EHIP;
     sp.walk_off = woff;
     sp.positions = positions;

@@ -72,9 +72,9 @@ def test_ragged_sizes(m):
 TUNES = [
     dict(chain_bytes=16), dict(chain_bytes=48), dict(chain_bytes=128), dict(chain_bytes=1024),
     dict(chain_bytes=4096), dict(chain_bytes=65536),
-    dict(chains_per_lane=1), dict(chains_per_lane=2),
-    dict(waves_per_group=1), dict(waves_per_group=2, chains_per_lane=1),
-    dict(waves_per_group=3, chain_bytes=2000 // 16 * 16, chains_per_lane=2),
+    dict(line_bytes=64), dict(line_bytes=128), dict(chains_per_lane=2, line_bytes=64),
+    dict(waves_per_group=1), dict(waves_per_group=2, line_bytes=64), dict(waves_per_group=8),
+    dict(waves_per_group=3, chain_bytes=2000 // 16 * 16, chains_per_lane=2, line_bytes=64),
 ]
 
 

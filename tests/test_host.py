@@ -96,6 +96,10 @@ def test_count_argument_checks_run_before_launch():
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
     t = api.tune(chains_per_lane=3)
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    t = api.tune(chains_per_lane=2, line_bytes=128)  # a shape the library does not build
+    assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    t = api.tune(line_bytes=96)
+    assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
     t = api.tune()
     t.reserved[1] = 5
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
