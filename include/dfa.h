@@ -54,8 +54,8 @@ typedef struct dfa_tune {
     int32_t waves_per_group; /* 64-lane waves per workgroup, 1..8 */
     int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 (or 2 with
                               * 64-byte rounds) */
-    int32_t dfas_per_group;  /* batched scans: automata resident per workgroup, 1..64 */
-    int32_t tile_bytes;      /* batched scans: text bytes per work item (multiple of 1024) */
+    int32_t dfas_per_group;  /* batched scans: automata walked together: 4, 8 or 16 */
+    int32_t tile_bytes;      /* unused, must be zero */
     int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
     int32_t reserved[3];     /* must be zero */
 } dfa_tune;
@@ -107,6 +107,64 @@ int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
               int64_t *count, int64_t *positions, int64_t cap,
               void *workspace, int64_t workspace_bytes,
               const dfa_tune *tune, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched: many patterns over many texts in one launch.                    */
+/* ------------------------------------------------------------------------ */
+
+/* Texts are segments of one buffer: segment s is text[seg_off[s] .. seg_off[s+1]-1]
+ * and no match crosses a segment border.  Patterns are given by their tables
+ * from dfa_build, stored back to back on the device: pattern j has length m[j]
+ * and its table starts at byte table_off[j] (a multiple of 4) of `tables`.
+ * Work pair k asks for the number of occurrences of pattern pair_pat[k] in
+ * segment pair_seg[k].  Every pattern keeps its own automaton and its own
+ * m-1 overlap, so patterns of different lengths are counted exactly (the
+ * equal-length restriction of the merged automaton of Sec. III.A does not
+ * apply).  Segments of the same pattern group are read once per workgroup for
+ * all automata of the group.
+ *
+ * Two steps, so that the second can be captured in a HIP graph and replayed:
+ *   dfa_batch_prepare  host: validates the arrays (all host memory), packs
+ *                      patterns into groups and tiles into work items, and
+ *                      uploads that plan into `workspace` (device, 256-byte
+ *                      aligned).  With workspace == NULL it only fills `plan`
+ *                      (including plan->workspace_bytes).  Synchronises `stream`.
+ *   dfa_batch_run      device only: zeroes counts[0..npairs-1] (int64, device)
+ *                      and launches the scan.  `text` (device, n >= plan->text_bytes
+ *                      bytes, 16-byte aligned) and `tables` (device, tables_bytes
+ *                      >= plan->tables_bytes) must be the buffers the plan
+ *                      describes; the workspace must hold the plan.  Asynchronous,
+ *                      allocates nothing, no memset nodes.
+ * dfa_count_batch = prepare + run.  All return DFA_OK, DFA_EINVAL,
+ * DFA_ENOSPACE or DFA_EHIP. */
+typedef struct dfa_batch_plan {
+    int64_t nitems;          /* work items: (tile of a segment, pattern group) */
+    int64_t ngroups;         /* pattern groups */
+    int64_t npairs;          /* counters written by dfa_batch_run */
+    int64_t text_bytes;      /* bytes the segments span (seg_off[nseg]) */
+    int64_t tables_bytes;    /* bytes of `tables` the referenced tables span */
+    int64_t workspace_bytes; /* device bytes the plan occupies */
+    int64_t items_offset;    /* layout of the plan inside the workspace */
+    int32_t dfas_per_group;  /* automata walked together per work item */
+    int32_t waves_per_group; /* 64-lane waves per workgroup */
+    int32_t reserved[4];
+} dfa_batch_plan;
+
+int dfa_batch_prepare(const int64_t *seg_off, int32_t nseg, const int64_t *table_off,
+                      const int32_t *m, int32_t npat, const int32_t *pair_seg,
+                      const int32_t *pair_pat, int64_t npairs, void *workspace,
+                      int64_t workspace_bytes, const dfa_tune *tune, dfa_batch_plan *plan,
+                      void *stream);
+
+int dfa_batch_run(const uint8_t *text, int64_t n, const uint8_t *tables, int64_t tables_bytes,
+                  const void *workspace, const dfa_batch_plan *plan, int64_t *counts, void *stream);
+
+int dfa_count_batch(const uint8_t *text, int64_t n, const int64_t *seg_off, int32_t nseg,
+                    const uint8_t *tables, int64_t tables_bytes, const int64_t *table_off,
+                    const int32_t *m, int32_t npat,
+                    const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
+                    int64_t *counts, void *workspace, int64_t workspace_bytes,
+                    const dfa_tune *tune, void *stream);
 
 #ifdef __cplusplus
 }

@@ -42,10 +42,27 @@ class Tune(ctypes.Structure):
     ]
 
 
+class BatchPlan(ctypes.Structure):
+    """dfa_batch_plan: filled by dfa_batch_prepare, read by dfa_batch_run."""
+    _fields_ = [
+        ("nitems", ctypes.c_int64),
+        ("ngroups", ctypes.c_int64),
+        ("npairs", ctypes.c_int64),
+        ("text_bytes", ctypes.c_int64),
+        ("tables_bytes", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+        ("items_offset", ctypes.c_int64),
+        ("dfas_per_group", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
 _TuneP = ctypes.POINTER(Tune)
+_PlanP = ctypes.POINTER(BatchPlan)
 
 # name -> (restype, argtypes); mirrors include/dfa.h
 SIGNATURES = {
@@ -55,6 +72,11 @@ SIGNATURES = {
     "dfa_build": (ctypes.c_int, [_vp, _i32, _vp]),
     "dfa_count_workspace_bytes": (_i64, [_i64, _i32, _i32, _TuneP]),
     "dfa_count": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP, _vp]),
+    "dfa_batch_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
+                                         _PlanP, _vp]),
+    "dfa_batch_run": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _PlanP, _vp, _vp]),
+    "dfa_count_batch": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _i64,
+                                       _vp, _vp, _i64, _TuneP, _vp]),
 }
 
 
@@ -177,6 +199,74 @@ def positions(text, table, m: int, cap: Optional[int] = None, t: Optional[Tune] 
     count_async(text, table, m, out, pos, cap, ws, t=t, stream=stream)
     c = int(out.item())
     return c, pos[:min(c, int(cap))]
+
+
+# ---------------------------------------------------------------------------
+# batched scans
+# ---------------------------------------------------------------------------
+
+class PatternSet:
+    """Automata for a list of patterns: built on the host, uploaded once as one
+    device buffer of back-to-back tables."""
+
+    def __init__(self, patterns, device="cuda"):
+        self.patterns = [bytes(p) for p in patterns]
+        tabs = [build_table(p) for p in self.patterns]
+        self.m = np.array([len(p) for p in self.patterns], dtype=np.int32)
+        sizes = np.array([t.size for t in tabs], dtype=np.int64)
+        self.table_off = np.zeros(len(tabs), dtype=np.int64)
+        if len(tabs) > 1:
+            self.table_off[1:] = np.cumsum(sizes)[:-1]
+        blob = np.concatenate([t.reshape(-1) for t in tabs]) if tabs else np.zeros(256, np.uint8)
+        self.tables = to_device(blob, device)
+
+    def __len__(self):
+        return len(self.patterns)
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(np.asarray(a, dtype=dt))
+
+
+class Batch:
+    """A prepared batch: (segments, pattern set, pairs) planned once; run() is
+    device-only and may be captured in a HIP graph and replayed."""
+
+    def __init__(self, seg_off, pset: PatternSet, pair_seg, pair_pat, t: Optional[Tune] = None,
+                 stream=None):
+        torch = _torch()
+        self.seg_off = _np(seg_off, np.int64)
+        self.pair_seg = _np(pair_seg, np.int32)
+        self.pair_pat = _np(pair_pat, np.int32)
+        self.pset = pset
+        self.plan = BatchPlan()
+        self._prep(None, 0, t, stream)
+        dev = pset.tables.device
+        self.workspace = torch.empty(max(1, self.plan.workspace_bytes), dtype=torch.uint8, device=dev)
+        self._prep(self.workspace.data_ptr(), self.workspace.numel(), t, stream)
+        self.counts = torch.zeros(max(1, self.pair_seg.size), dtype=torch.int64, device=dev)
+
+    def _prep(self, ws, wsb, t, stream):
+        p = self.pset
+        _check(lib.dfa_batch_prepare(self.seg_off.ctypes.data, self.seg_off.size - 1, p.table_off.ctypes.data,
+                                     p.m.ctypes.data, len(p), self.pair_seg.ctypes.data,
+                                     self.pair_pat.ctypes.data, self.pair_seg.size, ws, wsb, _tune_ptr(t),
+                                     ctypes.byref(self.plan), _stream_handle(stream)))
+
+    def run(self, text, stream=None):
+        """Enqueue the scan; counts land in self.counts (device int64)."""
+        _check(lib.dfa_batch_run(text.data_ptr() if text.numel() else None, text.numel(),
+                                 self.pset.tables.data_ptr(), self.pset.tables.numel(),
+                                 self.workspace.data_ptr(),
+                                 ctypes.byref(self.plan), self.counts.data_ptr(), _stream_handle(stream)))
+        return self.counts[:self.pair_seg.size]
+
+
+def count_batch(text, seg_off, pset: PatternSet, pair_seg, pair_pat, t: Optional[Tune] = None,
+                stream=None) -> np.ndarray:
+    """Per-pair occurrence counts (synchronises)."""
+    b = Batch(seg_off, pset, pair_seg, pair_pat, t, stream)
+    return b.run(text, stream).cpu().numpy()
 
 
 def exported_symbols() -> Sequence[str]:

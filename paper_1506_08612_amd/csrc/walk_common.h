@@ -1,0 +1,123 @@
+// Device-side building blocks shared by the automaton scan kernels of libdfa
+// (gfx950): the LDS table layout and step, the wave-level match count, and
+// the coalesced fetch + LDS transpose that gives every lane consecutive bytes
+// of its own walk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dfa.h"
+
+namespace dfa_dev {
+
+constexpr int kRow = DFA_ALPHABET + 24;  // LDS bytes per table row (256 columns + bank padding)
+constexpr int kWave = 64;
+
+// 16 text bytes as a native 4 x u32 register vector
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Geometry of one round: every walk receives LINE consecutive bytes (U units
+// of 16 bytes); one wave-wide 16-byte load covers 64/U walks.  The round is
+// transposed through a wave-private LDS buffer of 64 rows of LINE bytes per
+// walk slot, then walked one 16-byte unit at a time straight from LDS.
+template <int LINE>
+struct Geo {
+    static constexpr int U = LINE / 16;     // units per walk per round
+    static constexpr int kPer = kWave / U;  // walks per wave load
+    // XOR swizzle of the unit index by buffer row: any 8 consecutive lanes
+    // reading the same unit index hit 8 different 16-byte bank groups
+    __device__ static __forceinline__ int swz(int row) { return (row / (8 / U)) % U; }
+};
+
+__host__ __device__ inline int table_lds_rows_bytes(int rows) { return (rows * kRow + 15) & ~15; }
+
+// Orders this lane's LDS accesses against the other lanes' of the same wave:
+// LDS executes one wave's instructions in order, so waiting for the lane's
+// own outstanding LDS operations is enough; the clobber stops the compiler
+// from moving memory accesses across.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// The kernels declare no static LDS, so dynamic LDS (and with it the tables,
+// placed first) starts at LDS address 0.  Reading a table through an absolute
+// LDS address keeps the step's address one 24-bit multiply-add.  `q` is a row
+// number: the row of state q of a table whose rows start at row `base` is
+// base + q, and entries hold row numbers.
+typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+__device__ __forceinline__ uint32_t table_step(uint32_t q, uint32_t c) {
+    return *reinterpret_cast<lds_u8 *>(uintptr_t(__umul24(q, uint32_t(kRow)) + c));
+}
+
+// acc += number of lanes of the wave with `hit` set: one compare into a lane
+// mask, then a scalar bit count and add.  Written out so that the running
+// sum stays one scalar register (the compiler otherwise parks every step's
+// partial count in a register of its own).
+__device__ __forceinline__ void add_hits(uint32_t &acc, bool hit) {
+    const unsigned long long mask = __ballot(hit);
+    uint32_t tmp;
+    uint32_t a = __builtin_amdgcn_readfirstlane(acc);  // the count is wave-uniform
+    asm("s_bcnt1_i32_b64 %1, %2\n\ts_add_u32 %0, %0, %1" : "+s"(a), "=&s"(tmp) : "s"(mask) : "scc");
+    acc = a;
+}
+
+// 16 bytes at text[a..a+15]; bytes at or past n read as 0 (a byte outside
+// every pattern: it sends the automaton to q0 and never completes a match).
+__device__ __forceinline__ v4u load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
+    if (a + 16 <= n) return *reinterpret_cast<const v4u *>(text + a);
+    v4u v = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (a + i < n) v[i >> 2] |= uint32_t(text[a + i]) << (8 * (i & 3));
+    return v;
+}
+
+// Fetch round r of a wave's walks into registers.  The wave's walk w of slot
+// s starts at byte wbase + (64 s + w) S.  Load j of slot s covers the walks
+// 64 s + j kPer + lane/U (unit lane % U of each): U lanes read one LINE-byte
+// piece, so every load is made of whole, aligned pieces.  `lane_off` is
+// (lane / U) * S + 16 (lane % U).
+template <int K, int LINE, bool GUARDED>
+__device__ __forceinline__ void fetch_round(v4u (&pf)[K][Geo<LINE>::U], const uint8_t *text, int64_t n,
+                                            int64_t wbase, int64_t S, uint32_t lane_off, int r) {
+    using G = Geo<LINE>;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int j = 0; j < G::U; ++j) {
+            // wave-uniform base of this load, plus a 32-bit per-lane offset
+            const int64_t ub = wbase + int64_t(s * kWave + j * G::kPer) * S + int64_t(r) * LINE;
+            if (GUARDED)
+                pf[s][j] = load_unit_guarded(text, n, ub + int64_t(lane_off));
+            else
+                pf[s][j] = *reinterpret_cast<const v4u *>(text + ub + lane_off);
+        }
+    }
+}
+
+// Registers -> LDS: slot s of the wave's round lands in rows 64 s .. 64 s + 63
+// of the wave's buffer, one row of LINE bytes per walk.
+template <int K, int LINE>
+__device__ __forceinline__ void stage_round(const v4u (&pf)[K][Geo<LINE>::U], v4u *xb, int lane) {
+    using G = Geo<LINE>;
+    const int lrow = lane / G::U, lunit = lane % G::U;
+    wave_lds_sync();  // the previous round's reads of this buffer are done
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int j = 0; j < G::U; ++j) {
+            const int row = j * G::kPer + lrow;
+            xb[(s * kWave + row) * G::U + (lunit ^ G::swz(row))] = pf[s][j];
+        }
+    }
+    wave_lds_sync();
+}
+
+// Unit u (bytes 16u .. 16u + 15 of the round) of the lane's own walk in slot s.
+template <int LINE>
+__device__ __forceinline__ v4u unit_of(const v4u *xb, int s, int lane, int u) {
+    using G = Geo<LINE>;
+    return xb[(s * kWave + lane) * G::U + (u ^ G::swz(lane))];
+}
+
+}  // namespace dfa_dev

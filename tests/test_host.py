@@ -141,3 +141,59 @@ def test_decomposition_counts_every_match_once(S):
         m = int(rng.integers(1, 12))
         p = np.frombuffer(b"AC", np.uint8)[rng.integers(0, 2, m)].tobytes()
         assert model_scan(t, p, S) == oracle.occurrences(t, p).tolist()
+
+
+# ----------------------------------------------------------------------------------------
+# batched scans: planning and argument checks run on the host (workspace == NULL is a size
+# query that launches nothing)
+# ----------------------------------------------------------------------------------------
+
+def _plan(seg_off, ms, pair_seg, pair_pat, t=None):
+    seg_off = np.asarray(seg_off, np.int64)
+    ms = np.asarray(ms, np.int32)
+    toff = np.zeros(ms.size, np.int64)
+    if ms.size > 1:
+        toff[1:] = np.cumsum((ms.astype(np.int64) + 1) * 256)[:-1]
+    ps = np.asarray(pair_seg, np.int32)
+    pp = np.asarray(pair_pat, np.int32)
+    plan = api.BatchPlan()
+    rc = api.lib.dfa_batch_prepare(seg_off.ctypes.data, seg_off.size - 1, toff.ctypes.data, ms.ctypes.data,
+                                   ms.size, ps.ctypes.data, pp.ctypes.data, ps.size, None, 0,
+                                   ctypes.byref(t) if t is not None else None, ctypes.byref(plan), None)
+    return rc, plan
+
+
+def test_batch_plan_groups_and_items():
+    # one 1 MB segment, 20 patterns of length 30 (31 rows each): 8 fit 256 rows -> 3 groups
+    rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)))
+    assert rc == api.DFA_OK, api.last_error()
+    assert plan.ngroups == 3 and plan.npairs == 20 and plan.text_bytes == 1 << 20
+    assert plan.nitems % plan.ngroups == 0 and plan.nitems >= plan.ngroups
+    assert plan.workspace_bytes > 0 and plan.dfas_per_group == 8
+    # rows cap the group: patterns of length 127 take 128 rows, two per group
+    rc, plan = _plan([0, 4096], [127] * 5, [0] * 5, list(range(5)))
+    assert rc == api.DFA_OK and plan.ngroups == 3
+    # segments of length 0 contribute no work
+    rc, plan = _plan([0, 0, 0], [4], [0, 1], [0, 0])
+    assert rc == api.DFA_OK and plan.nitems == 0 and plan.npairs == 2
+    rc, plan = _plan([0, 1000], [8] * 3, [0] * 3, [0, 1, 2], api.tune(dfas_per_group=4, waves_per_group=2))
+    assert rc == api.DFA_OK and plan.dfas_per_group == 4 and plan.waves_per_group == 2
+
+
+def test_batch_plan_rejects_bad_arguments():
+    assert _plan([0, 10, 5], [4], [0], [0])[0] == api.DFA_EINVAL          # seg_off decreasing
+    assert _plan([0, 10], [0], [0], [0])[0] == api.DFA_EINVAL             # m < 1
+    assert _plan([0, 10], [256], [0], [0])[0] == api.DFA_EINVAL           # m > 255
+    assert _plan([0, 10], [4], [1], [0])[0] == api.DFA_EINVAL             # segment out of range
+    assert _plan([0, 10], [4], [0], [3])[0] == api.DFA_EINVAL             # pattern out of range
+    assert _plan([0, 10], [4], [0], [0], api.tune(dfas_per_group=5))[0] == api.DFA_EINVAL
+    assert _plan([0, 10], [4], [0], [0], api.tune(waves_per_group=9))[0] == api.DFA_EINVAL
+    plan = api.BatchPlan()
+    assert api.lib.dfa_batch_run(None, 0, None, 0, None, ctypes.byref(plan), None, None) == api.DFA_EINVAL
+    rc, plan = _plan([0, 100], [4], [0], [0])
+    assert plan.tables_bytes == 5 * 256
+    fake = 1 << 20
+    # text shorter than the segments span
+    assert api.lib.dfa_batch_run(fake, 50, fake, 4096, fake, ctypes.byref(plan), fake, None) == api.DFA_EINVAL
+    # tables buffer shorter than the tables the plan refers to
+    assert api.lib.dfa_batch_run(fake, 100, fake, 1000, fake, ctypes.byref(plan), fake, None) == api.DFA_EINVAL
