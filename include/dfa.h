@@ -54,7 +54,7 @@ typedef struct dfa_tune {
     int32_t waves_per_group; /* 64-lane waves per workgroup, 1..8 */
     int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 (or 2 with
                               * 64-byte rounds) */
-    int32_t dfas_per_group;  /* batched scans: automata walked together: 4, 8 or 16 */
+    int32_t dfas_per_group;  /* batched scans: automata walked together: 2, 4, 8 or 16 */
     int32_t tile_bytes;      /* unused, must be zero */
     int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
     int32_t reserved[3];     /* must be zero */
@@ -115,7 +115,8 @@ int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
 /* Texts are segments of one buffer: segment s is text[seg_off[s] .. seg_off[s+1]-1]
  * and no match crosses a segment border.  Patterns are given by their tables
  * from dfa_build, stored back to back on the device: pattern j has length m[j]
- * and its table starts at byte table_off[j] (a multiple of 4) of `tables`.
+ * (1..254) and its table starts at byte table_off[j] (a multiple of 4) of
+ * `tables`.
  * Work pair k asks for the number of occurrences of pattern pair_pat[k] in
  * segment pair_seg[k].  Every pattern keeps its own automaton and its own
  * m-1 overlap, so patterns of different lengths are counted exactly (the

@@ -42,6 +42,7 @@ using namespace dfa_dev;
 
 constexpr int kLine = 128;          // bytes of every walk fetched per round
 constexpr int kMaxRows = 256;       // rows of one group's shared row space (states fit a byte)
+constexpr int kNullRow = kMaxRows - 1;  // self-looping row of the padding automata; never final
 constexpr int kMaxGroup = 16;       // automata per group, at most
 constexpr int kXcds = 8;            // workgroups are dealt to the XCDs in turn
 constexpr int64_t kMinSpan = 256;   // shortest walk span the planner uses
@@ -56,7 +57,7 @@ struct DevDfa {
 };
 
 struct DevGroup {
-    int32_t ndfa;
+    int32_t ndfa;  // real automata; slots ndfa.. are padding that sits in kNullRow
     int32_t rows;  // rows used
     int32_t minm, maxm;
     DevDfa dfa[kMaxGroup];
@@ -79,25 +80,29 @@ struct BatchParams {
     unsigned long long *counts;
 };
 
-// Walk 16 bytes with all G automata.  Byte b of word w is byte jb + 4w + b of
-// the walk; with GUARD only bytes below the automaton's own length count.
+// Walk 16 bytes with all G automata (padding automata included: a uniform
+// branch per automaton would cut the unrolled steps into blocks and lose the
+// overlap of the G independent table reads).  Byte b of word w is byte
+// jb + 4w + b of the walk; with GUARD only bytes below the automaton's own
+// length count.
 template <int G, bool GUARD>
 __device__ __forceinline__ void walk_unit_multi(const v4u &t, uint32_t (&q)[G], const uint32_t (&fin)[G],
-                                                const uint32_t (&len)[G], int ndfa, uint32_t jb,
-                                                uint32_t (&acc)[G]) {
+                                                const uint32_t (&len)[G], uint32_t jb, uint32_t (&acc)[G]) {
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const uint32_t c = (t[w] >> (8 * b)) & 0xffu;
+            // all G table reads of this byte go out before the first count, so
+            // G reads are in flight at once
+#pragma unroll
+            for (int d = 0; d < G; ++d) q[d] = table_step(q[d], c);
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads grouped ahead of the counts
 #pragma unroll
             for (int d = 0; d < G; ++d) {
-                if (d < ndfa) {
-                    q[d] = table_step(q[d], c);
-                    bool hit = q[d] == fin[d];
-                    if (GUARD) hit = hit && (jb + uint32_t(4 * w + b) < len[d]);
-                    add_hits(acc[d], hit);
-                }
+                bool hit = q[d] == fin[d];
+                if (GUARD) hit = hit && (jb + uint32_t(4 * w + b) < len[d]);
+                add_hits(acc[d], hit);
             }
         }
     }
@@ -125,6 +130,8 @@ __global__ __launch_bounds__(512) void k_batch(BatchParams p) {
         for (int i = threadIdx.x; i < words; i += blockDim.x)
             *reinterpret_cast<uint32_t *>(smem + (dd.base_row + (i >> 6)) * kRow + 4 * (i & 63)) = tg[i] + add;
     }
+    for (int i = threadIdx.x; i < DFA_ALPHABET / 4; i += blockDim.x)  // padding: every byte stays in kNullRow
+        *reinterpret_cast<uint32_t *>(smem + kNullRow * kRow + 4 * i) = uint32_t(kNullRow) * 0x01010101u;
     __syncthreads();
 
     uint32_t q[G], fin[G], len[G], acc[G];
@@ -135,10 +142,11 @@ __global__ __launch_bounds__(512) void k_batch(BatchParams p) {
     own = own < 0 ? 0 : (own > S ? S : own);
 #pragma unroll
     for (int d = 0; d < G; ++d) {
-        const int m = d < ndfa ? gr.dfa[d].m : 1;
-        const int base = d < ndfa ? gr.dfa[d].base_row : 0;
+        const bool real = d < ndfa;
+        const int m = real ? gr.dfa[d].m : 1;
+        const int base = real ? gr.dfa[d].base_row : kNullRow;
         q[d] = uint32_t(base);
-        fin[d] = uint32_t(base + m);
+        fin[d] = real ? uint32_t(base + m) : 0x100u;  // no row is 0x100
         int64_t L = 0;
         if (own > 0) {
             L = own + m - 1;
@@ -170,9 +178,9 @@ __global__ __launch_bounds__(512) void k_batch(BatchParams p) {
                 if (u + 1 < Geo<kLine>::U) nxt = unit_of<kLine>(xb, 0, lane, u + 1);
                 const int jb = r * kLine + 16 * u;
                 if (jb + 16 <= safe)
-                    walk_unit_multi<G, false>(cur, q, fin, len, ndfa, uint32_t(jb), acc);
+                    walk_unit_multi<G, false>(cur, q, fin, len, uint32_t(jb), acc);
                 else if (jb < int(S) + maxm - 1)
-                    walk_unit_multi<G, true>(cur, q, fin, len, ndfa, uint32_t(jb), acc);
+                    walk_unit_multi<G, true>(cur, q, fin, len, uint32_t(jb), acc);
                 cur = nxt;
             }
         }
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(512) void k_batch(BatchParams p) {
             v4u cur = unit_of<kLine>(xb, 0, lane, 0), nxt = cur;
             for (int u = 0; u < Geo<kLine>::U; ++u) {
                 if (u + 1 < Geo<kLine>::U) nxt = unit_of<kLine>(xb, 0, lane, u + 1);
-                walk_unit_multi<G, true>(cur, q, fin, len, ndfa, uint32_t(r * kLine + 16 * u), acc);
+                walk_unit_multi<G, true>(cur, q, fin, len, uint32_t(r * kLine + 16 * u), acc);
                 cur = nxt;
             }
         }
@@ -217,6 +225,7 @@ __global__ void k_zero_counts(unsigned long long *c, int64_t n) {
 // ---------------------------------------------------------------------------
 
 const void *batch_fn(int G) {
+    if (G == 2) return reinterpret_cast<const void *>(&k_batch<2>);
     if (G == 4) return reinterpret_cast<const void *>(&k_batch<4>);
     if (G == 8) return reinterpret_cast<const void *>(&k_batch<8>);
     if (G == 16) return reinterpret_cast<const void *>(&k_batch<16>);
@@ -256,8 +265,9 @@ int plan_batch(const int64_t *seg_off, int32_t nseg, const int64_t *table_off, c
                 dfa::set_error("tune.reserved must be zero");
                 return DFA_EINVAL;
             }
-        if (t->dfas_per_group && t->dfas_per_group != 4 && t->dfas_per_group != 8 && t->dfas_per_group != 16) {
-            dfa::set_error("tune.dfas_per_group=%d must be 4, 8 or 16 (or 0)", t->dfas_per_group);
+        if (t->dfas_per_group && t->dfas_per_group != 2 && t->dfas_per_group != 4 && t->dfas_per_group != 8 &&
+            t->dfas_per_group != 16) {
+            dfa::set_error("tune.dfas_per_group=%d must be 2, 4, 8 or 16 (or 0)", t->dfas_per_group);
             return DFA_EINVAL;
         }
         if (t->waves_per_group < 0 || t->waves_per_group > 8) {
@@ -270,7 +280,7 @@ int plan_batch(const int64_t *seg_off, int32_t nseg, const int64_t *table_off, c
             return DFA_EINVAL;
         }
     }
-    hp.G = (t && t->dfas_per_group) ? t->dfas_per_group : 8;
+    hp.G = (t && t->dfas_per_group) ? t->dfas_per_group : 4;
     hp.waves = (t && t->waves_per_group) ? t->waves_per_group : 8;
     const int64_t fixed_span = t ? t->chain_bytes : 0;
     for (int32_t s = 0; s <= nseg - 1; ++s)
@@ -280,9 +290,10 @@ int plan_batch(const int64_t *seg_off, int32_t nseg, const int64_t *table_off, c
         }
     hp.text_bytes = nseg > 0 ? seg_off[nseg] : 0;
     for (int32_t j = 0; j < npat; ++j) {
-        if (m[j] < 1 || m[j] > DFA_MAX_M || table_off[j] < 0 || (table_off[j] & 3)) {
-            dfa::set_error("dfa_batch: pattern %d: m=%d or table_off=%lld invalid (4-byte aligned)", j, m[j],
-                           (long long)table_off[j]);
+        // one row of the 256-row space is the padding automata's, so m <= 254
+        if (m[j] < 1 || m[j] > kNullRow - 1 || table_off[j] < 0 || (table_off[j] & 3)) {
+            dfa::set_error("dfa_batch: pattern %d: m=%d (batched scans take 1..%d) or table_off=%lld "
+                           "(4-byte aligned) invalid", j, m[j], kNullRow - 1, (long long)table_off[j]);
             return DFA_EINVAL;
         }
     }
@@ -322,7 +333,7 @@ int plan_batch(const int64_t *seg_off, int32_t nseg, const int64_t *table_off, c
         };
         for (int64_t k : ks) {
             const int mm = m[pair_pat[k]];
-            if (cur.ndfa == hp.G || cur.rows + mm + 1 > kMaxRows) flush();
+            if (cur.ndfa == hp.G || cur.rows + mm + 1 > kNullRow) flush();
             DevDfa &d = cur.dfa[cur.ndfa++];
             d.table_off = table_off[pair_pat[k]];
             d.m = mm;

@@ -164,15 +164,21 @@ def _plan(seg_off, ms, pair_seg, pair_pat, t=None):
 
 
 def test_batch_plan_groups_and_items():
-    # one 1 MB segment, 20 patterns of length 30 (31 rows each): 8 fit 256 rows -> 3 groups
+    # one 1 MB segment, 20 patterns of length 30 (31 rows each): 4 per group by default,
+    # 8 per group fit 255 rows
     rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)))
     assert rc == api.DFA_OK, api.last_error()
-    assert plan.ngroups == 3 and plan.npairs == 20 and plan.text_bytes == 1 << 20
-    assert plan.nitems % plan.ngroups == 0 and plan.nitems >= plan.ngroups
-    assert plan.workspace_bytes > 0 and plan.dfas_per_group == 8
-    # rows cap the group: patterns of length 127 take 128 rows, two per group
-    rc, plan = _plan([0, 4096], [127] * 5, [0] * 5, list(range(5)))
+    assert plan.ngroups == 5 and plan.npairs == 20 and plan.text_bytes == 1 << 20
+    rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)), api.tune(dfas_per_group=8))
     assert rc == api.DFA_OK and plan.ngroups == 3
+    assert plan.nitems % plan.ngroups == 0 and plan.nitems >= plan.ngroups
+    assert plan.workspace_bytes > 0 and plan.dfas_per_group == 4
+    # rows cap the group: patterns of length 126 take 127 rows, two per group (255 rows
+    # are usable)
+    rc, plan = _plan([0, 4096], [126] * 5, [0] * 5, list(range(5)))
+    assert rc == api.DFA_OK and plan.ngroups == 3
+    rc, plan = _plan([0, 4096], [127] * 4, [0] * 4, list(range(4)))
+    assert rc == api.DFA_OK and plan.ngroups == 4
     # segments of length 0 contribute no work
     rc, plan = _plan([0, 0, 0], [4], [0, 1], [0, 0])
     assert rc == api.DFA_OK and plan.nitems == 0 and plan.npairs == 2
@@ -184,6 +190,7 @@ def test_batch_plan_rejects_bad_arguments():
     assert _plan([0, 10, 5], [4], [0], [0])[0] == api.DFA_EINVAL          # seg_off decreasing
     assert _plan([0, 10], [0], [0], [0])[0] == api.DFA_EINVAL             # m < 1
     assert _plan([0, 10], [256], [0], [0])[0] == api.DFA_EINVAL           # m > 255
+    assert _plan([0, 10], [255], [0], [0])[0] == api.DFA_EINVAL           # batched: m <= 254
     assert _plan([0, 10], [4], [1], [0])[0] == api.DFA_EINVAL             # segment out of range
     assert _plan([0, 10], [4], [0], [3])[0] == api.DFA_EINVAL             # pattern out of range
     assert _plan([0, 10], [4], [0], [0], api.tune(dfas_per_group=5))[0] == api.DFA_EINVAL
