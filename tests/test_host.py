@@ -169,10 +169,10 @@ def test_batch_plan_groups_and_items():
     rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)))
     assert rc == api.DFA_OK, api.last_error()
     assert plan.ngroups == 5 and plan.npairs == 20 and plan.text_bytes == 1 << 20
-    rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)), api.tune(dfas_per_group=8))
-    assert rc == api.DFA_OK and plan.ngroups == 3
     assert plan.nitems % plan.ngroups == 0 and plan.nitems >= plan.ngroups
     assert plan.workspace_bytes > 0 and plan.dfas_per_group == 4
+    rc, plan = _plan([0, 1 << 20], [30] * 20, [0] * 20, list(range(20)), api.tune(dfas_per_group=8))
+    assert rc == api.DFA_OK and plan.ngroups == 3 and plan.dfas_per_group == 8
     # rows cap the group: patterns of length 126 take 127 rows, two per group (255 rows
     # are usable)
     rc, plan = _plan([0, 4096], [126] * 5, [0] * 5, list(range(5)))
