@@ -34,6 +34,7 @@
 
 #include "dfa.h"
 #include "dfa_internal.h"
+#include "launch_util.h"
 #include "walk_common.h"
 
 namespace {
@@ -236,11 +237,7 @@ size_t batch_lds_bytes(int waves) {
     return size_t(table_lds_rows_bytes(kMaxRows)) + size_t(waves) * kWave * kLine;
 }
 
-bool hip_ok(hipError_t e, const char *what) {
-    if (e == hipSuccess) return true;
-    dfa::set_error("%s: %s", what, hipGetErrorString(e));
-    return false;
-}
+using dfa::hip_ok;
 
 struct HostPlan {
     std::vector<DevGroup> groups;
@@ -472,13 +469,7 @@ extern "C" int dfa_batch_run(const uint8_t *text, int64_t n, const uint8_t *tabl
         dfa::clear_error();
         return DFA_OK;
     }
-    static std::mutex mu;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(batch_lds_bytes(8))),
-                    "hipFuncSetAttribute"))
-            return DFA_EHIP;
-    }
+    if (!dfa::allow_lds(fn, int(batch_lds_bytes(8)))) return DFA_EHIP;
     const uint8_t *ws = reinterpret_cast<const uint8_t *>(workspace);
     BatchParams bp{};
     bp.text = text;

@@ -37,6 +37,7 @@
 
 #include "dfa.h"
 #include "dfa_internal.h"
+#include "launch_util.h"
 #include "walk_common.h"
 
 namespace {
@@ -491,11 +492,7 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
     return true;
 }
 
-bool hip_ok(hipError_t e, const char *what) {
-    if (e == hipSuccess) return true;
-    dfa::set_error("%s: %s", what, hipGetErrorString(e));
-    return false;
-}
+using dfa::hip_ok;
 
 int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) {
     const void *fn = pick_scan(pl.K, pl.line, mode);
@@ -503,15 +500,8 @@ int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) 
         dfa::set_error("no kernel for K=%d line=%d", pl.K, pl.line);
         return DFA_EINVAL;
     }
-    static std::mutex mu;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        // allow the largest table (m = 255) with the largest workgroup
-        if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(scan_lds_bytes(8, 1, 128, DFA_MAX_M))),
-                    "hipFuncSetAttribute"))
-            return DFA_EHIP;
-    }
+    // allow the largest table (m = 255) with the largest workgroup
+    if (!dfa::allow_lds(fn, int(scan_lds_bytes(8, 1, 128, DFA_MAX_M)))) return DFA_EHIP;
     void *args[] = {const_cast<ScanParams *>(&sp)};
     if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(pl.blocks)), dim3(pl.wpg * kWave), args, pl.lds, st),
                 "k_scan launch"))

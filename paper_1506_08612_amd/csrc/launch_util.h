@@ -1,0 +1,36 @@
+// Host-side launch helpers shared by the HIP translation units of libdfa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <set>
+#include <utility>
+
+#include "dfa_internal.h"
+
+namespace dfa {
+
+inline bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return false;
+}
+
+// Raise a kernel's dynamic-LDS limit once per (device, kernel), so that later
+// calls -- including calls made while a stream is being captured into a
+// graph -- only enqueue launches.
+inline bool allow_lds(const void *fn, int bytes) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = 0;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({dev, fn})) return true;
+    if (!hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes), "hipFuncSetAttribute"))
+        return false;
+    done.insert({dev, fn});
+    return true;
+}
+
+}  // namespace dfa

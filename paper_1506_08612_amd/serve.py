@@ -1,0 +1,289 @@
+"""Continuous-batching query server for (text, pattern set) requests.
+
+A request is one text and 1..k patterns; its answer is the occurrence count
+of every pattern in the text.  The server
+
+* admits requests in arrival order as long as their text fits the free space
+  of a device text arena (admission by HBM footprint); a request that does not
+  fit waits until finished requests free their bytes;
+* uploads admitted texts on a copy stream (pinned host memory) while earlier
+  batches run on the compute stream;
+* fuses every admitted request whose upload has been issued into ONE batched
+  scan launch: each request's text is a segment of the arena (gaps between
+  texts are segments nobody asks about), each (request, pattern) is a pair;
+* keeps at most `max_inflight` fused launches on the device; requests that
+  arrive while others run are admitted as slots and memory free up and join
+  the next launch, so their work overlaps on the device;
+* records, per request: arrival, admission, launch and completion times.
+
+`mode="fifo"` is the one-query-per-launch baseline on the same trace: one
+request at a time, upload, plan, launch, wait.
+
+Everything device-side is the library's batched scan (dfa_batch_prepare /
+dfa_batch_run); this module only schedules.
+"""
+from __future__ import annotations
+
+import bisect
+import dataclasses
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import api
+
+ALIGN = 256  # arena placement granularity (the scan wants 16-byte aligned segments)
+
+
+class Arena:
+    """First-fit allocator over [0, size) with coalescing frees (host bookkeeping only)."""
+
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.free = [(0, self.size)]  # sorted (offset, length)
+        self.used = 0
+
+    @staticmethod
+    def _round(n: int) -> int:
+        return max(ALIGN, (int(n) + ALIGN - 1) // ALIGN * ALIGN)
+
+    def alloc(self, n: int) -> Optional[int]:
+        need = self._round(n)
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= need:
+                if ln == need:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + need, ln - need)
+                self.used += need
+                return off
+        return None
+
+    def release(self, off: int, n: int) -> None:
+        need = self._round(n)
+        self.used -= need
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, need))
+        # coalesce with neighbours
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (self.free[i][0], self.free[i][1] + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+
+def segments_for(placed, arena_size: int):
+    """Segment boundaries covering [0, end of the last text) for texts placed at
+    (offset, length): every text is a segment; the gaps between texts are segments
+    too (no pair refers to them).  Returns (seg_off, seg_of_text)."""
+    order = sorted(range(len(placed)), key=lambda i: placed[i][0])
+    seg_off = [0]
+    seg_of = [0] * len(placed)
+    for i in order:
+        off, ln = placed[i]
+        if off > seg_off[-1]:
+            seg_off.append(off)  # gap segment
+        seg_of[i] = len(seg_off) - 1
+        seg_off.append(off + ln)
+    return np.array(seg_off, dtype=np.int64), seg_of
+
+
+@dataclasses.dataclass
+class Request:
+    qid: int
+    text: np.ndarray       # uint8 host text
+    patterns: list         # list[bytes]
+    arrival: float = 0.0   # seconds after the start of the run
+
+
+@dataclasses.dataclass
+class Result:
+    qid: int
+    counts: np.ndarray
+    arrival: float
+    admitted: float
+    launched: float
+    done: float
+    text_bytes: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Job:
+    __slots__ = ("req", "pinned", "offset", "tables", "admitted", "copied", "launched")
+
+
+class Server:
+    def __init__(self, arena_bytes: int = 4 << 30, max_inflight: int = 2, tune: Optional[api.Tune] = None,
+                 device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.arena_bytes = int(arena_bytes)
+        self.arena_buf = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
+        self.copy_stream = torch.cuda.Stream(device=self.device)     # default priority
+        self.compute_stream = torch.cuda.Stream(device=self.device)  # default priority
+        self.max_inflight = max_inflight
+        self.tune = tune
+
+    # -- helpers --------------------------------------------------------------------------
+    def _pin(self, req: Request):
+        t = self.torch.from_numpy(np.ascontiguousarray(req.text, dtype=np.uint8))
+        return t.pin_memory() if t.numel() else t
+
+    def _tables(self, req: Request):
+        return [api.build_table(p) for p in req.patterns]
+
+    def _launch(self, jobs: List[_Job], now):
+        """One fused batched scan over the jobs' texts; returns (event, counts tensor, spans)."""
+        torch = self.torch
+        placed = [(j.offset, j.req.text.size) for j in jobs]
+        seg_off, seg_of = segments_for(placed, self.arena_bytes)
+        blobs, m, pair_seg, pair_pat, spans = [], [], [], [], []
+        toff = 0
+        table_off = []
+        for ji, j in enumerate(jobs):
+            first = len(pair_seg)
+            for p, tab in zip(j.req.patterns, j.tables):
+                blobs.append(tab.reshape(-1))
+                table_off.append(toff)
+                toff += tab.size
+                m.append(len(p))
+                pair_seg.append(seg_of[ji])
+                pair_pat.append(len(pair_pat))
+            spans.append((first, len(pair_seg)))
+        blob = np.concatenate(blobs) if blobs else np.zeros(256, np.uint8)
+        with torch.cuda.stream(self.copy_stream):
+            tables = torch.from_numpy(blob).pin_memory().to(self.device, non_blocking=True)
+        so = np.ascontiguousarray(seg_off)
+        toff_a = np.array(table_off, np.int64)
+        m_a = np.array(m, np.int32)
+        ps_a = np.array(pair_seg, np.int32)
+        pp_a = np.array(pair_pat, np.int32)
+        plan = api.BatchPlan()
+        api._check(api.lib.dfa_batch_prepare(so.ctypes.data, so.size - 1, toff_a.ctypes.data, m_a.ctypes.data,
+                                             m_a.size, ps_a.ctypes.data, pp_a.ctypes.data, ps_a.size, None, 0,
+                                             api._tune_ptr(self.tune), api.ctypes.byref(plan), None))
+        ws = torch.empty(max(1, plan.workspace_bytes), dtype=torch.uint8, device=self.device)
+        # the plan upload synchronises the copy stream (texts and tables are on it too)
+        api._check(api.lib.dfa_batch_prepare(so.ctypes.data, so.size - 1, toff_a.ctypes.data, m_a.ctypes.data,
+                                             m_a.size, ps_a.ctypes.data, pp_a.ctypes.data, ps_a.size,
+                                             ws.data_ptr(), ws.numel(), api._tune_ptr(self.tune),
+                                             api.ctypes.byref(plan), self.copy_stream.cuda_stream))
+        counts = torch.empty(max(1, ps_a.size), dtype=torch.int64, device=self.device)
+        self.compute_stream.wait_stream(self.copy_stream)
+        api._check(api.lib.dfa_batch_run(self.arena_buf.data_ptr(), self.arena_bytes, tables.data_ptr(),
+                                         tables.numel(), ws.data_ptr(), api.ctypes.byref(plan),
+                                         counts.data_ptr(), self.compute_stream.cuda_stream))
+        ev = torch.cuda.Event()
+        ev.record(self.compute_stream)
+        # keep the per-launch buffers alive until the event has fired
+        return ev, counts, spans, (tables, ws)
+
+    # -- the loop -------------------------------------------------------------------------
+    def serve(self, trace: List[Request], mode: str = "continuous", time_scale: float = 1.0) -> List[Result]:
+        """Replay `trace` (arrival times in seconds, scaled by time_scale) and return one
+        Result per request, in qid order."""
+        assert mode in ("continuous", "fifo")
+        torch = self.torch
+        reqs = sorted(trace, key=lambda r: r.arrival)
+        for r in reqs:
+            if r.text.size > self.arena_bytes:
+                raise ValueError(f"request {r.qid}: text of {r.text.size} bytes exceeds the arena")
+        pinned = {r.qid: self._pin(r) for r in reqs}
+        tables = {r.qid: self._tables(r) for r in reqs}
+        arena = Arena(self.arena_bytes)
+        pending: List[Request] = []
+        admitted: List[_Job] = []
+        inflight = []  # (event, counts, spans, jobs, keep)
+        results = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        clock = lambda: (time.perf_counter() - t0)  # noqa: E731
+        while len(results) < len(reqs):
+            now = clock()
+            while nxt < len(reqs) and reqs[nxt].arrival * time_scale <= now:
+                pending.append(reqs[nxt])
+                nxt += 1
+            progressed = False
+            # completions
+            still = []
+            for ev, counts, spans, jobs, keep in inflight:
+                if ev.query():
+                    c = counts.cpu().numpy()
+                    tdone = clock()
+                    for (a, b), j in zip(spans, jobs):
+                        results[j.req.qid] = Result(j.req.qid, c[a:b].copy(), j.req.arrival * time_scale,
+                                                    j.admitted, j.launched, tdone, int(j.req.text.size))
+                        if j.req.text.size:
+                            arena.release(j.offset, j.req.text.size)
+                    progressed = True
+                else:
+                    still.append((ev, counts, spans, jobs, keep))
+            inflight = still
+            # admission by footprint (arrival order; fifo: one request in the system)
+            while pending and (mode == "continuous" or (not admitted and not inflight)):
+                r = pending[0]
+                off = arena.alloc(r.text.size) if r.text.size else 0
+                if off is None:
+                    break
+                pending.pop(0)
+                j = _Job()
+                j.req, j.pinned, j.offset, j.tables = r, pinned[r.qid], off, tables[r.qid]
+                j.admitted = clock()
+                if r.text.size:
+                    with torch.cuda.stream(self.copy_stream):
+                        self.arena_buf[off:off + r.text.size].copy_(j.pinned, non_blocking=True)
+                admitted.append(j)
+                progressed = True
+                if mode == "fifo":
+                    break
+            # launch everything admitted as one fused batch when a slot is free
+            if admitted and len(inflight) < (self.max_inflight if mode == "continuous" else 1):
+                tl = clock()
+                for j in admitted:
+                    j.launched = tl
+                ev, counts, spans, keep = self._launch(admitted, tl)
+                inflight.append((ev, counts, spans, admitted, keep))
+                admitted = []
+                progressed = True
+            if not progressed:
+                if inflight:
+                    time.sleep(20e-6)
+                elif nxt < len(reqs):
+                    wait = reqs[nxt].arrival * time_scale - clock()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+        torch.cuda.synchronize()
+        return [results[r.qid] for r in sorted(trace, key=lambda r: r.qid)]
+
+
+def summarize(results: List[Result]) -> dict:
+    lat = np.array([r.latency for r in results]) * 1e3
+    t_first = min(r.arrival for r in results)
+    t_last = max(r.done for r in results)
+    total = sum(r.text_bytes for r in results)
+    return {
+        "queries": len(results),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "mean_ms": round(float(lat.mean()), 3),
+        "text_GBps": round(total / max(1e-9, t_last - t_first) / 1e9, 3),
+        "makespan_s": round(t_last - t_first, 4),
+    }
+
+
+def make_trace(nq: int, rate_hz: float, seed: int = 5, len_lo: float = 1e4, len_hi: float = 5e8,
+               pmax: int = 64, mlo: int = 4, mhi: int = 64, n_frac: float = 0.02) -> List[Request]:
+    """Poisson arrivals of queries: text length log-uniform in [len_lo, len_hi] (ACGT with 'N' runs),
+    1..pmax patterns with lengths uniform in [mlo, mhi], half drawn from the text."""
+    from . import synth
+    out = []
+    for q in synth.query_trace(nq, rate_hz, seed, len_lo, len_hi, pmax, mlo, mhi):
+        text, pats = synth.query_text(q, n_frac=n_frac)
+        out.append(Request(len(out), text, pats, q.arrival_s))
+    return out

@@ -246,7 +246,7 @@ class Query:
     arrival_s: float
     text_len: int
     seed: int
-    patterns: list
+    pattern_lens: list
 
 
 def query_trace(nq: int, rate_hz: float, seed: int = 5, len_lo: float = 1e4, len_hi: float = 5e8,
@@ -271,7 +271,7 @@ def query_text(q: Query, n_frac: float = 0.02, n_run_mean: float = 5000):
     text = genome_like(q.text_len, q.seed, n_frac, n_run_mean)
     rng = np.random.default_rng([q.seed, 0x5150])
     pats = []
-    for i, m in enumerate(q.patterns):
+    for i, m in enumerate(q.pattern_lens):
         p = None
         if i % 2 == 0:
             p, _ = drawn_pattern(text, m, rng, tries=64)
