@@ -13,7 +13,18 @@ Also reported:
   HIP events on the launch stream; algorithmic bytes = the text read once;
 * cpu_baseline -- the CPU oracle (plain C, one thread) timed on a bounded
   prefix of the same text for the same five patterns;
-* per-pattern latency p50/p99 of the full call over the timed steps.
+* per-pattern latency p50/p99 of the full call over the timed steps;
+* batched -- 1 GB GC-41% text x 1024 patterns (lengths 4..64, half drawn from
+  the text) in one batched launch (autotuned shape, replayed from a HIP graph)
+  against the same GPU running one count-only launch per pattern, in
+  pattern-bytes/s;
+* segmented -- 2000 contig-like segments (log-normal lengths, median 200 kB,
+  ~2 GB, 2% 'N' runs), 1..16 patterns each, one batched launch;
+* serving -- Poisson arrivals of (text, patterns) queries (text log-uniform in
+  [10 kB, 500 MB], 1..64 patterns of length 4..64) at 80% of the capacity the
+  server sustains in a closed loop; p50/p99 latency (arrival to counts on the
+  host, upload included) and text GB/s, against the one-query-per-launch FIFO
+  form on the same trace.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -73,6 +84,90 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def _events_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
+    from paper_1506_08612_amd import autotune, graph
+    log(f"batched: {n} bytes x {npat} patterns")
+    w = synth.many_patterns(n=n, npat=npat)
+    d = api.to_device(w.text)
+    ps = api.PatternSet(w.patterns)
+    out = torch.empty(npat, dtype=torch.int64, device=d.device)
+    tabs = [ps.tables[int(o):int(o) + (int(mm) + 1) * 256] for o, mm in zip(ps.table_off, ps.m)]
+
+    def one_per_launch():
+        for j in range(npat):
+            api.count_async(d, tabs[j], int(ps.m[j]), out[j:j + 1])
+
+    base_ms = _events_ms(torch, one_per_launch, 1)
+    ref = out.cpu().numpy()
+    pairs = (np.zeros(npat, np.int64), np.arange(npat))
+    t, entry = autotune.tune_batch(d, [0, n], ps, *pairs, reps=1)
+    b = api.Batch([0, n], ps, *pairs, t)
+    g = graph.GraphedBatch(d, b)
+    ms = _events_ms(torch, g.replay, 3)
+    equal = bool(np.array_equal(b.counts.cpu().numpy()[:npat], ref))
+    pb = n * npat
+    return {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), counts only",
+            "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1),
+            "one_per_launch_pattern_bytes_per_s": round(pb / (base_ms * 1e-3), 1),
+            "speedup_vs_one_per_launch": round(base_ms / ms, 3),
+            "ms": round(ms, 3), "one_per_launch_ms": round(base_ms, 3),
+            "tune": entry["tune"], "groups": int(b.plan.ngroups), "items": int(b.plan.nitems),
+            "counts_equal_one_per_launch": equal}
+
+
+def bench_segmented(torch, api, synth):
+    from paper_1506_08612_amd import graph
+    log("segmented: 2000 contig-like segments")
+    w = synth.uneven_segments()
+    d = api.to_device(w.text)
+    ps = api.PatternSet(w.patterns)
+    b = api.Batch(w.seg_off, ps, w.pair_seg, w.pair_pat)
+    g = graph.GraphedBatch(d, b)
+    ms = _events_ms(torch, g.replay, 3)
+    seg_len = np.diff(w.seg_off)
+    pb = int(seg_len[w.pair_seg].sum())
+    return {"workload": f"{seg_len.size} segments, {int(w.seg_off[-1])} B, {w.pair_seg.size} (segment, pattern) pairs",
+            "ms": round(ms, 3), "text_GBps": round(int(w.seg_off[-1]) / ms / 1e6, 1),
+            "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems)}
+
+
+def bench_serving(torch, nq):
+    from paper_1506_08612_amd import serve
+    log(f"serving: {nq} queries")
+    trace = serve.make_trace(nq, rate_hz=1.0, seed=5)
+    srv = serve.Server(arena_bytes=8 << 30)
+    srv.serve(trace[:4], mode="continuous")  # warm up
+    closed = [serve.Request(r.qid, r.text, r.patterns, 0.0) for r in trace]
+    cap = srv.serve(closed, mode="continuous")
+    makespan = max(r.done for r in cap)
+    capacity = nq / makespan
+    rate = 0.8 * capacity
+    # the seeded Poisson trace has rate 1/s: dividing its arrival times by `rate` rescales it
+    timed = [serve.Request(r.qid, r.text, r.patterns, r.arrival / rate) for r in trace]
+    res = srv.serve(timed, mode="continuous")
+    cont = serve.summarize(res)
+    fifo_res = srv.serve(timed, mode="fifo")
+    fifo = serve.summarize(fifo_res)
+    same = all(np.array_equal(x.counts, y.counts) for x, y in zip(res, fifo_res))
+    return {"workload": f"{nq} queries, text log-uniform [1e4, 5e8] B (2% N runs), 1..64 patterns m=U[4,64], "
+                        f"Poisson arrivals at 0.8 x closed-loop capacity",
+            "capacity_qps": round(capacity, 2), "rate_qps": round(rate, 2),
+            "continuous": cont, "one_query_per_launch": fifo,
+            "answers_equal_across_modes": bool(same)}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +180,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many bytes (counter calibration)")
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="skip the batched, segmented and serving measurements")
+    ap.add_argument("--serve-queries", type=int, default=64)
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -196,7 +294,8 @@ def main(argv=None) -> int:
         src = torch.empty(a.copy_calibration, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         src.fill_(1)
-        dst.copy_(src)
+        dst.copy_(src)                 # runtime blit copy: reads and writes n bytes
+        torch.add(src, 1, out=dst)     # elementwise kernel: reads and writes n bytes
         torch.cuda.synchronize()
         del src, dst
 
@@ -222,6 +321,17 @@ def main(argv=None) -> int:
             g = g[g <= sn - len(p)]
             ok &= bool(np.array_equal(g, oracle_pos[i]))
         parity_sample = ok
+
+    extra = {}
+    if not a.skip_extra:
+        del dtext
+        torch.cuda.empty_cache()
+        extra["batched"] = bench_batched(torch, api, synth)
+        torch.cuda.empty_cache()
+        extra["segmented"] = bench_segmented(torch, api, synth)
+        torch.cuda.empty_cache()
+        extra["serving"] = bench_serving(torch, a.serve_queries)
+        torch.cuda.empty_cache()
 
     lat_all = np.array([x for L in lat for x in L])
     out = {
@@ -264,6 +374,7 @@ def main(argv=None) -> int:
         "parity_sample_vs_oracle": parity_sample,
         "h2d_GBps": round(n / h2d_s / 1e9, 2),
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
     return 0
 

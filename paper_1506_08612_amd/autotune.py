@@ -20,13 +20,13 @@ from typing import Dict, Iterable, List, Optional
 from . import api
 
 SCAN_CANDIDATES: List[Dict[str, int]] = [
-    dict(),  # library default
-    dict(line_bytes=128, chain_bytes=1024),
-    dict(line_bytes=128, chain_bytes=4096),
-    dict(line_bytes=64, chain_bytes=1024),
-    dict(line_bytes=64, chain_bytes=2048),
-    dict(line_bytes=128, waves_per_group=2),
-    dict(chains_per_lane=2, line_bytes=64),
+    dict(),  # library default (64-byte rounds, workgroup size from occupancy)
+    dict(waves_per_group=2),
+    dict(waves_per_group=4),
+    dict(waves_per_group=8),
+    dict(chain_bytes=1024),
+    dict(chain_bytes=2048),
+    dict(line_bytes=128),
 ]
 
 BATCH_CANDIDATES: List[Dict[str, int]] = [

@@ -9,13 +9,16 @@
 // cannot reach the final state before it has read m bytes of its own span).
 // Every lane of a wave runs K independent walks, interleaved for latency
 // hiding; the 64*K walks of a wave are consecutive spans of the text.
+// Spans are whole 128-byte lines, so a walk's loads never share a line with
+// another round's.
 //
 // Data movement.  Each round a wave fetches the next 128 bytes of each of its
 // walks with coalesced 16-byte loads (8 lanes read one 128-byte line), writes
 // them to a wave-private LDS buffer, and reads them back transposed so that
 // every lane holds 128 consecutive bytes of its own walk in registers.  The
 // loads for round r+1 are in flight while round r is walked.  HBM traffic is
-// the text once plus the m-1 overlap bytes per walk.
+// the text once plus the m-1 overlap bytes per walk (fetched as the first
+// ceil((m-1)/16) units of the next span's first line).
 //
 // Automaton step (Sec. III.B).  The (m+1) x 256 byte-indexed table lives in
 // LDS with rows padded to 280 bytes, so the rows of the low, most visited
@@ -32,7 +35,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <map>
 #include <mutex>
 
 #include "dfa.h"
@@ -85,6 +90,10 @@ struct WalkLane {
 template <int K, int MODE, bool GUARD>
 __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
                                           uint32_t &acc, WalkLane (&wl)[K], const ScanParams &p) {
+    if constexpr (MODE == kCount && !GUARD && K == 1) {
+        walk16_count(q[0], t[0], acc, m);
+        return;
+    }
     uint32_t q0[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) q0[s] = q[s];
@@ -162,7 +171,52 @@ __device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q
     }
 }
 
-template <int K, int LINE, int MODE>
+// Overlap units loaded ahead (H): 1 unit covers m <= 17, 4 units m <= 65.
+// The kernel is instantiated for both so that short patterns keep 12 more
+// registers free (one more wave per SIMD).
+constexpr int halo_units_for(int m) { return m <= 17 ? 1 : 4; }
+
+// The first H units of the overlap of each of the lane's walks, taken right
+// after round 0 is staged: the overlap of walk (slot s, lane l) is the start
+// of walk (s, l + 1), row s * 64 + l + 1 of the wave's buffer.  The last walk
+// of the wave (whose neighbour is another wave's) and units past the ones the
+// buffer holds (`valid` < H only for spans shorter than a round) are loaded
+// from memory, with u clamped to hu - 1 so that every address stays inside
+// the overlap.
+template <int K, int LINE, int H>
+__device__ __forceinline__ void grab_halo(v4u (&h)[K][H], const v4u *xb, int lane, const uint8_t *text, int64_t g0,
+                                          int64_t S, int hu, int valid) {
+    using G = Geo<LINE>;
+    const int last = hu > 0 ? hu - 1 : 0;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int rho = s * kWave + lane + 1;
+        const bool in_buf = rho < K * kWave;
+        const int rr = in_buf ? rho : K * kWave - 1;
+        const int row = rr % kWave;
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            v4u v = xb[rr * G::U + (u ^ G::swz(row))];
+            if (hu > 0 && (!in_buf || u >= valid))
+                v = *reinterpret_cast<const v4u *>(text + (g0 + s * kWave + lane + 1) * S + 16 * (u < last ? u : last));
+            h[s][u] = v;
+        }
+    }
+}
+
+// Round r of the wave's walks (in-bounds path): rounds before the last use the
+// lane's own unit offset, the last one the clamped offset; r past the last
+// round loads the text's first line (a cache hit whose values are never used).
+template <int K, int LINE>
+__device__ __forceinline__ void fetch_round_or_none(v4u (&pf)[K][Geo<LINE>::U], const uint8_t *text, int64_t wb,
+                                                    int64_t S, uint32_t off, uint32_t off_last, uint32_t off_none,
+                                                    int r, int rlast) {
+    const bool real = r <= rlast;  // wave-uniform
+    fetch_round<K, LINE, false>(pf, text, 0, real ? wb : 0, real ? S : 0,
+                                r < rlast ? off : (real ? off_last : off_none), real ? r : 0);
+}
+
+template <int K, int LINE, int MODE, int H>
 __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -221,27 +275,85 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     // whole wave in bounds: every load of every round lies inside the text
     const int64_t glast = g0 + kWave * K - 1;
     const bool full = glast < p.nwalks && glast * p.S + int64_t(p.rounds) * LINE <= p.n;
-    const int lastlen = int(p.S + p.m - 1 - int64_t(p.rounds - 1) * LINE);  // bytes walked in the last round
     uint32_t acc = 0;
 
     if (full) {
-        // loads run two rounds ahead of the walk: pa holds even rounds, pb odd
-        // ones.  Fetches past the last round re-read the last round (an L2
-        // hit), so that both buffers are always written and stay in registers.
-        const int rlast = p.rounds - 1;
+        // The span [0, S) streams in R rounds; the overlap [S, S + m - 1) is
+        // the start of the next span, which the neighbouring lane (the next
+        // walk) receives in round 0.  Right after round 0 is staged, each lane
+        // copies the first H units of its neighbour's row out of the wave's
+        // buffer and keeps them in registers until the end of the walk; only
+        // the wave's last walk, whose neighbour belongs to another wave,
+        // loads them from memory.  Fetching the overlap at the end of the
+        // walk instead would miss in L2 and cost a whole line of HBM per
+        // walk.  Units past H (m > 65) are loaded at the end.
+        const int R = int((p.S + LINE - 1) / LINE);
+        const int rlast = R - 1;
+        const int lastlen = int(p.S - int64_t(rlast) * LINE);  // bytes of the last round (LINE unless S is not a
+                                                               // multiple of LINE)
+        // Loads run two rounds ahead of the walk: pa holds even rounds, pb odd
+        // ones.  A short last round fetches only the units it walks: lanes past
+        // them repeat the last unit's address, a load of the same line.  A
+        // fetch past the last round reads the first line of the text instead
+        // (always cached), so that both buffers are always written and stay
+        // in registers without touching another line of HBM.  With 64-byte
+        // rounds, rounds r + 2 and r + 3 are the two halves of the walks' next
+        // 128-byte lines; both are requested back to back so that the second
+        // half finds the line still in L2 (requested one round apart, the
+        // shared line is evicted first and read twice).
+        const uint32_t ulast = uint32_t(lastlen + 15) / 16;
+        const uint32_t lane_unit = uint32_t(lane % G::U);
+        const uint32_t off_last = lane_off - 16u * lane_unit + 16u * (lane_unit < ulast ? lane_unit : ulast - 1);
+        const uint32_t off_none = 16u * lane_unit;
+        const int64_t wb = g0 * p.S;
         v4u pa[K][G::U], pb[K][G::U];
-        fetch_round<K, LINE, false>(pa, p.text, p.n, g0 * p.S, p.S, lane_off, 0);
-        fetch_round<K, LINE, false>(pb, p.text, p.n, g0 * p.S, p.S, lane_off, rlast < 1 ? rlast : 1);
-        for (int r = 0; r < p.rounds; r += 2) {
+        fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
+        fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
+        const int hu = (p.m - 1 + 15) / 16;  // overlap units
+        v4u halo[K][H];
+        // round 0 (and 1), then the steady state from round 2
+        stage_round<K, LINE>(pa, xb, lane);
+        grab_halo<K, LINE, H>(halo, xb, lane, p.text, g0, p.S, hu, rlast == 0 ? int(ulast) : G::U);
+        if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+        walk_round<K, LINE, MODE, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
+        if (rlast >= 1) {
+            stage_round<K, LINE>(pb, xb, lane);
+            if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
+            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
+                                             p);
+        }
+        for (int r = 2; r < R; r += 2) {
             stage_round<K, LINE>(pa, xb, lane);
-            fetch_round<K, LINE, false>(pa, p.text, p.n, g0 * p.S, p.S, lane_off, r + 2 < rlast ? r + 2 : rlast);
+            if (LINE == 128)
+                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
             walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
                                              acc, wl, p);
             if (r + 1 > rlast) break;
             stage_round<K, LINE>(pb, xb, lane);
-            fetch_round<K, LINE, false>(pb, p.text, p.n, g0 * p.S, p.S, lane_off, r + 3 < rlast ? r + 3 : rlast);
+            if (LINE == 64)
+                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
+            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
             walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
                                              r + 1 == rlast ? lastlen : LINE, acc, wl, p);
+        }
+        // the overlap, from registers, then (m > 65) the rest of it from memory
+        const uint32_t hb = uint32_t(p.S);
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            if (u < hu) {
+                v4u t[K];
+#pragma unroll
+                for (int s = 0; s < K; ++s) t[s] = halo[s][u];
+                walk_unit<K, MODE, true>(t, q, m, hb + 16u * u, acc, wl, p);
+            }
+        }
+        for (int u = H; u < hu; ++u) {
+            v4u t[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s)
+                t[s] = *reinterpret_cast<const v4u *>(p.text + (g0 + s * kWave + lane + 1) * p.S + 16 * u);
+            walk_unit<K, MODE, true>(t, q, m, hb + 16u * u, acc, wl, p);
         }
     } else {
         v4u pf[K][G::U];
@@ -379,18 +491,20 @@ struct Plan {
     size_t lds = 0;
 };
 
-template <int K, int LINE>
+template <int K, int LINE, int H>
 const void *scan_fn(int mode) {
-    if (mode == kCount) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCount>);
-    if (mode == kCountPerWalk) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWalk>);
-    return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions>);
+    if (mode == kCount) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCount, H>);
+    if (mode == kCountPerWalk) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWalk, H>);
+    return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions, H>);
 }
 
-// the (walks per lane, bytes per round) shapes compiled into the library
-const void *pick_scan(int K, int line, int mode) {
-    if (K == 1 && line == 128) return scan_fn<1, 128>(mode);
-    if (K == 1 && line == 64) return scan_fn<1, 64>(mode);
-    if (K == 2 && line == 64) return scan_fn<2, 64>(mode);
+// the (walks per lane, bytes per round) shapes compiled into the library, each
+// with the overlap prefetch depth for the pattern length
+const void *pick_scan(int K, int line, int mode, int m) {
+    const bool h1 = halo_units_for(m) == 1;
+    if (K == 1 && line == 128) return h1 ? scan_fn<1, 128, 1>(mode) : scan_fn<1, 128, 4>(mode);
+    if (K == 1 && line == 64) return h1 ? scan_fn<1, 64, 1>(mode) : scan_fn<1, 64, 4>(mode);
+    if (K == 2 && line == 64) return scan_fn<2, 64, 4>(mode);
     return nullptr;
 }
 
@@ -402,14 +516,23 @@ int64_t min_span(const dfa_tune *t) {
     return (t && t->chain_bytes > 0) ? t->chain_bytes : dfa::kMinChainBytes;
 }
 
+// gfx950 compute unit: 4 SIMDs, 512 vector registers per lane per SIMD, at
+// most 8 waves per SIMD, 160 KiB of LDS
+constexpr int kSimdsPerCu = 4;
+constexpr int kVgprsPerLane = 512;
+constexpr int kMaxWavesPerSimd = 8;
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 constexpr int kDefaultK = 1;
-constexpr int kDefaultLine = 128;
+constexpr int kDefaultLine = 64;
 constexpr int kDefaultWpg = 4;
 
 // Default span of one walk.  Many short walks (far more workgroups than fit
 // on the device at once) let the hardware dispatcher balance the load; the
-// span stays long against m so the overlap re-read (m-1 bytes) stays small.
-constexpr int64_t kSpanTarget = 2048;
+// span stays long against m so that the overlap (m-1 bytes walked twice) and
+// the per-workgroup table load stay small: 1 KiB up to m = 32, 2 KiB above.
+constexpr int64_t kSpanShort = 1024;
+constexpr int64_t kSpanLong = 2048;
 
 bool check_tune(const dfa_tune *t) {
     if (!t) return true;
@@ -432,7 +555,7 @@ bool check_tune(const dfa_tune *t) {
     }
     const int line = t->line_bytes ? t->line_bytes : kDefaultLine;
     const int K = t->chains_per_lane ? t->chains_per_lane : kDefaultK;
-    if (t->chains_per_lane < 0 || !pick_scan(K, line, kCount)) {
+    if (t->chains_per_lane < 0 || !pick_scan(K, line, kCount, 1)) {
         dfa::set_error("tune: chains_per_lane=%d with line_bytes=%d is not a built shape "
                        "(1 with 64 or 128, 2 with 64)", t->chains_per_lane, line);
         return false;
@@ -471,19 +594,62 @@ WsLayout ws_layout(int64_t nw) {
 }
 int64_t workspace_for(int64_t nw) { return ws_layout(nw).total; }
 
+// Vector registers per lane of a compiled kernel (0 if unknown).
+int kernel_vgprs(const void *fn) {
+    static std::mutex mu;
+    static std::map<const void *, int> seen;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = seen.find(fn);
+    if (it != seen.end()) return it->second;
+    hipFuncAttributes a{};
+    const int regs = hipFuncGetAttributes(&a, fn) == hipSuccess ? a.numRegs : 0;
+    if (regs <= 0) (void)hipGetLastError();
+    seen[fn] = regs;
+    return regs;
+}
+
+// Default waves per workgroup: the smallest of 2, 4, 8 whose workgroups keep
+// at least 90% of the waves a CU can hold by registers resident, given the
+// LDS each one needs (its transpose buffers plus its own copy of the table).
+// Small workgroups refill a CU at a finer grain; large ones share one table
+// among more waves, which matters once the table is large (long patterns).
+int default_wpg(const void *fn, int K, int line, int m) {
+    const int regs = kernel_vgprs(fn);
+    if (regs <= 0) return kDefaultWpg;
+    const int per_simd = std::min(kMaxWavesPerSimd, kVgprsPerLane / int(dfa::round_up(regs, 8)));
+    const int by_regs = kSimdsPerCu * std::max(1, per_simd);
+    int waves[3], best = 0;
+    const int cand[3] = {2, 4, 8};
+    for (int i = 0; i < 3; ++i) {
+        const int groups = int(kLdsPerCu / scan_lds_bytes(cand[i], K, line, m));
+        waves[i] = std::min(by_regs, groups * cand[i]);
+        best = std::max(best, waves[i]);
+    }
+    for (int i = 0; i < 3; ++i)
+        if (10 * waves[i] >= 9 * best) return cand[i];
+    return kDefaultWpg;
+}
+
 bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
     pl.K = (t && t->chains_per_lane) ? t->chains_per_lane : kDefaultK;
     pl.line = (t && t->line_bytes) ? t->line_bytes : kDefaultLine;
-    pl.wpg = (t && t->waves_per_group) ? t->waves_per_group : kDefaultWpg;
+    if (t && t->waves_per_group) {
+        pl.wpg = t->waves_per_group;
+    } else {
+        const void *fn = pick_scan(pl.K, pl.line, mode, m);
+        pl.wpg = fn ? default_wpg(fn, pl.K, pl.line, m) : kDefaultWpg;
+    }
     pl.lds = scan_lds_bytes(pl.wpg, pl.K, pl.line, m);
     if (t && t->chain_bytes > 0) {
         pl.S = t->chain_bytes;
     } else {
-        // whole rounds: S + m - 1 fills R rounds up to less than 16 bytes
-        const int64_t halo = dfa::round_up(m - 1, 16);
-        int64_t R = dfa::ceil_div(kSpanTarget + m - 1, pl.line);
-        pl.S = R * pl.line - halo;
-        if (pl.S < dfa::kMinChainBytes) pl.S = dfa::round_up(dfa::kMinChainBytes, 16);
+        // whole lines: every walk starts on a 128-byte boundary (the text is
+        // 16-byte aligned, torch and hipMalloc give 256), so each round's
+        // loads cover exactly one cache line per walk.  A span that is not a
+        // multiple of the line makes every round straddle two lines; with
+        // hundreds of streaming waves per XCD the shared line is evicted from
+        // L2 before the next round needs it, and HBM reads double.
+        pl.S = dfa::round_up(m <= 32 ? kSpanShort : kSpanLong, 128);
     }
     pl.rounds = int(dfa::ceil_div(pl.S + m - 1, pl.line));
     pl.nwalks = n > 0 ? dfa::ceil_div(n, pl.S) : 0;
@@ -495,7 +661,7 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
 using dfa::hip_ok;
 
 int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) {
-    const void *fn = pick_scan(pl.K, pl.line, mode);
+    const void *fn = pick_scan(pl.K, pl.line, mode, sp.m);
     if (!fn) {
         dfa::set_error("no kernel for K=%d line=%d", pl.K, pl.line);
         return DFA_EINVAL;

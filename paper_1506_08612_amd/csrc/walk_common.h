@@ -61,6 +61,137 @@ __device__ __forceinline__ void add_hits(uint32_t &acc, bool hit) {
     acc = a;
 }
 
+// Sixteen automaton steps over one 16-byte unit, counting visits of the final
+// state, for the in-bounds count-only walk.  Each step computes the next LDS
+// address and issues the byte read first; the next text byte is extracted and
+// the previous state tested against the final state while the read is in
+// flight, so the dependent chain per byte is one multiply-add and one LDS read.
+// The read is waited for inside the same block.  States alternate between two
+// registers (the test reads the older one while the read fills the other); the
+// unit ends with the state in `q`, all sixteen states tested.
+__device__ __forceinline__ void walk16_count(uint32_t &q, const v4u &t, uint32_t &acc, uint32_t m) {
+    uint32_t qb, a, c, tmp;
+    unsigned long long mk;
+    uint32_t s = __builtin_amdgcn_readfirstlane(acc);
+    asm(
+        "v_bfe_u32 %[c], %[w0], 0, 8\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 8, 8\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "s_bcnt1_i32_b64 %[t], %[mk]\n\t"
+        "s_add_u32 %[acc], %[acc], %[t]\n\t"
+        : [q] "+v"(q), [qb] "=&v"(qb), [a] "=&v"(a), [c] "=&v"(c), [mk] "=&s"(mk), [t] "=&s"(tmp), [acc] "+s"(s)
+        : [w0] "v"(t.x), [w1] "v"(t.y), [w2] "v"(t.z), [w3] "v"(t.w), [m] "s"(m), [row] "s"(uint32_t(kRow))
+        : "scc");
+    acc = s;
+}
+
 // 16 bytes at text[a..a+15]; bytes at or past n read as 0 (a byte outside
 // every pattern: it sends the automaton to q0 and never completes a match).
 __device__ __forceinline__ v4u load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
