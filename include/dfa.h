@@ -55,7 +55,9 @@ typedef struct dfa_tune {
     int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 (or 2 with
                               * 64-byte rounds) */
     int32_t dfas_per_group;  /* batched scans: automata walked together: 2, 4, 8 or 16 */
-    int32_t tile_bytes;      /* unused, must be zero */
+    int32_t automaton_bytes; /* merged scans: LDS bytes one merged automaton may take
+                              * (its table, byte-class map and final-state counters);
+                              * decides how many patterns share one automaton */
     int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
     int32_t reserved[3];     /* must be zero */
 } dfa_tune;
@@ -166,6 +168,86 @@ int dfa_count_batch(const uint8_t *text, int64_t n, const int64_t *seg_off, int3
                     const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
                     int64_t *counts, void *workspace, int64_t workspace_bytes,
                     const dfa_tune *tune, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Merged multi-pattern automata (Sec. "Implementation Aspects", Fig. 4,    */
+/* Table 2): one automaton advances many patterns per byte.                 */
+/* ------------------------------------------------------------------------ */
+
+#define DFA_AC_MAX_STATES 65535 /* merged states are 16-bit */
+
+/* Host-only.  Builds the paper's improved Aho-Corasick automaton for patterns
+ * p_i = patterns[pat_off[i] .. pat_off[i] + pat_len[i] - 1], i < npat
+ * (1 <= pat_len[i] <= DFA_MAX_M; repeats allowed): one state per distinct
+ * prefix of the patterns, state 0 the empty prefix; entry (q, b) is the state
+ * of the longest suffix of (prefix of q) + b that is a prefix of some pattern,
+ * so failure links never have to be followed; every byte that occurs in no
+ * pattern leads to state 0.  States that report at least one pattern (a
+ * pattern is a suffix of their prefix) are numbered last, from *first_final on.
+ *   table        host, max_states x 256 uint16, row-major by state, or NULL
+ *                for a size query
+ *   first_final  host int32 or NULL: receives the first reporting state
+ *   out_off      host or NULL: nstates - first_final + 1 int32; the patterns
+ *   out_pat      reported by state f are out_pat[out_off[f - first_final] ..
+ *                out_off[f - first_final + 1] - 1] (indices i), room for out_cap
+ *   n_out        host int64 or NULL: receives the number of out_pat entries
+ * Returns the number of states (>= 2), or DFA_EINVAL (bad arguments, more
+ * than DFA_AC_MAX_STATES states) or DFA_ENOSPACE (table or out_pat too small). */
+int64_t dfa_ac_build(const uint8_t *patterns, const int64_t *pat_off, const int32_t *pat_len,
+                     int32_t npat, uint16_t *table, int64_t max_states, int32_t *first_final,
+                     int32_t *out_off, int32_t *out_pat, int64_t out_cap, int64_t *n_out);
+
+typedef struct dfa_merged_plan {
+    int64_t nitems;          /* work items: (tile of a segment, merged automaton) */
+    int64_t nautomata;       /* merged automata built */
+    int64_t nstates;         /* states over all automata */
+    int64_t nfinal;          /* reporting states over all automata */
+    int64_t npairs;          /* counters written by dfa_merged_run */
+    int64_t text_bytes;      /* bytes the segments span (seg_off[nseg]) */
+    int64_t workspace_bytes; /* device bytes the plan occupies (automata, items, visit counters) */
+    int64_t items_offset;    /* layout of the plan inside the workspace */
+    int64_t outputs_offset;
+    int64_t entries_offset;
+    int64_t visits_offset;
+    int32_t waves_per_group; /* 64-lane waves per workgroup */
+    int32_t lds_bytes;       /* dynamic LDS of the scan launch */
+    int32_t reserved[4];
+} dfa_merged_plan;
+
+/* Batched counting with merged automata: same question as the dfa_batch_*
+ * calls (pair k asks for the occurrences of pattern pair_pat[k] inside
+ * segment pair_seg[k]), but the patterns are passed as bytes
+ * (patterns[pat_off[j] ..], pat_len[j] in 1..DFA_MAX_M, host) and the pairs
+ * of each segment are merged into as few automata as the LDS budget
+ * (tune->automaton_bytes) allows, so that one table lookup per text byte
+ * advances all patterns of an automaton.  Each automaton is stored as a
+ * 256-entry byte-class map plus a 16-bit table with one column per class
+ * (every byte that occurs in none of its patterns is one class): the same
+ * transitions as the 256-column table of dfa_ac_build, in the space that lets
+ * thousands of states share LDS.  A walk owns the match starts of its span and
+ * reads max(m) - 1 bytes past it; a match that ends in that overlap is
+ * counted only if it starts inside the span (the start-position rule that
+ * makes patterns of unequal lengths exact).
+ *   dfa_merged_prepare  host: validates, builds the automata, plans the work
+ *                       and uploads everything into `workspace` (device,
+ *                       256-byte aligned); with workspace == NULL only fills
+ *                       `plan`.  Synchronises `stream`.
+ *   dfa_merged_run      device only: clears the counters it owns, zeroes
+ *                       counts[0..npairs-1] (int64, device, 8-byte aligned) and
+ *                       launches the scan and the count reduction; `text`
+ *                       (device, n >= plan->text_bytes, 16-byte aligned).
+ *                       Asynchronous, allocates nothing, no memset nodes; the
+ *                       workspace is written (calls that share it must not
+ *                       overlap).
+ * Both return DFA_OK, DFA_EINVAL, DFA_ENOSPACE or DFA_EHIP. */
+int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns,
+                       const int64_t *pat_off, const int32_t *pat_len, int32_t npat,
+                       const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
+                       void *workspace, int64_t workspace_bytes, const dfa_tune *tune,
+                       dfa_merged_plan *plan, void *stream);
+
+int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, const dfa_merged_plan *plan,
+                   int64_t *counts, void *stream);
 
 #ifdef __cplusplus
 }

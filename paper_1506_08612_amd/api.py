@@ -36,7 +36,7 @@ class Tune(ctypes.Structure):
         ("waves_per_group", ctypes.c_int32),
         ("chains_per_lane", ctypes.c_int32),
         ("dfas_per_group", ctypes.c_int32),
-        ("tile_bytes", ctypes.c_int32),
+        ("automaton_bytes", ctypes.c_int32),
         ("line_bytes", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 3),
     ]
@@ -58,11 +58,32 @@ class BatchPlan(ctypes.Structure):
     ]
 
 
+class MergedPlan(ctypes.Structure):
+    """dfa_merged_plan: filled by dfa_merged_prepare, read by dfa_merged_run."""
+    _fields_ = [
+        ("nitems", ctypes.c_int64),
+        ("nautomata", ctypes.c_int64),
+        ("nstates", ctypes.c_int64),
+        ("nfinal", ctypes.c_int64),
+        ("npairs", ctypes.c_int64),
+        ("text_bytes", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+        ("items_offset", ctypes.c_int64),
+        ("outputs_offset", ctypes.c_int64),
+        ("entries_offset", ctypes.c_int64),
+        ("visits_offset", ctypes.c_int64),
+        ("waves_per_group", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
 _TuneP = ctypes.POINTER(Tune)
 _PlanP = ctypes.POINTER(BatchPlan)
+_MPlanP = ctypes.POINTER(MergedPlan)
 
 # name -> (restype, argtypes); mirrors include/dfa.h
 SIGNATURES = {
@@ -77,6 +98,10 @@ SIGNATURES = {
     "dfa_batch_run": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _PlanP, _vp, _vp]),
     "dfa_count_batch": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _i64,
                                        _vp, _vp, _i64, _TuneP, _vp]),
+    "dfa_ac_build": (_i64, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp]),
+    "dfa_merged_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
+                                          _MPlanP, _vp]),
+    "dfa_merged_run": (ctypes.c_int, [_vp, _i64, _vp, _MPlanP, _vp, _vp]),
 }
 
 
@@ -105,8 +130,8 @@ def _check(rc: int) -> int:
 
 
 def tune(chain_bytes: int = 0, waves_per_group: int = 0, chains_per_lane: int = 0,
-         dfas_per_group: int = 0, tile_bytes: int = 0, line_bytes: int = 0) -> Tune:
-    return Tune(chain_bytes, waves_per_group, chains_per_lane, dfas_per_group, tile_bytes,
+         dfas_per_group: int = 0, automaton_bytes: int = 0, line_bytes: int = 0) -> Tune:
+    return Tune(chain_bytes, waves_per_group, chains_per_lane, dfas_per_group, automaton_bytes,
                 line_bytes)
 
 
@@ -266,6 +291,95 @@ def count_batch(text, seg_off, pset: PatternSet, pair_seg, pair_pat, t: Optional
                 stream=None) -> np.ndarray:
     """Per-pair occurrence counts (synchronises)."""
     b = Batch(seg_off, pset, pair_seg, pair_pat, t, stream)
+    return b.run(text, stream).cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# merged multi-pattern automata
+# ---------------------------------------------------------------------------
+
+def _pack_patterns(patterns):
+    pats = [bytes(p) for p in patterns]
+    lens = np.array([len(p) for p in pats], dtype=np.int32)
+    offs = np.zeros(len(pats), dtype=np.int64)
+    if len(pats) > 1:
+        offs[1:] = np.cumsum(lens[:-1])
+    blob = np.frombuffer(b"".join(pats) or b"\0", dtype=np.uint8).copy()
+    return pats, blob, offs, lens
+
+
+class AcTable:
+    """Host merged automaton from dfa_ac_build: table (nstates, 256) uint16, reporting
+    states from first_final on, and per reporting state the indices of its patterns."""
+
+    def __init__(self, table, first_final, out_off, out_pat):
+        self.table = table
+        self.first_final = int(first_final)
+        self.out_off = out_off
+        self.out_pat = out_pat
+
+    @property
+    def nstates(self) -> int:
+        return self.table.shape[0]
+
+    def outputs(self, q: int):
+        f = q - self.first_final
+        if f < 0:
+            return []
+        return self.out_pat[self.out_off[f]:self.out_off[f + 1]].tolist()
+
+
+def ac_build(patterns) -> AcTable:
+    """Host build of the merged automaton of `patterns` (1..255 bytes each)."""
+    pats, blob, offs, lens = _pack_patterns(patterns)
+    ff = ctypes.c_int32()
+    nout = ctypes.c_int64()
+    ns = _check(lib.dfa_ac_build(blob.ctypes.data, offs.ctypes.data, lens.ctypes.data, len(pats), None, 0,
+                                 ctypes.byref(ff), None, None, 0, ctypes.byref(nout)))
+    table = np.empty((ns, ALPHABET), dtype=np.uint16)
+    out_off = np.empty(ns - ff.value + 1, dtype=np.int32)
+    out_pat = np.empty(max(1, nout.value), dtype=np.int32)
+    _check(lib.dfa_ac_build(blob.ctypes.data, offs.ctypes.data, lens.ctypes.data, len(pats), table.ctypes.data, ns,
+                            ctypes.byref(ff), out_off.ctypes.data, out_pat.ctypes.data, out_pat.size,
+                            ctypes.byref(nout)))
+    return AcTable(table, ff.value, out_off, out_pat[:nout.value])
+
+
+class MergedBatch:
+    """Batched counting with merged automata: (segments, patterns, pairs) planned and
+    uploaded once; run() is device-only and may be captured in a HIP graph."""
+
+    def __init__(self, seg_off, patterns, pair_seg, pair_pat, t: Optional[Tune] = None, device="cuda",
+                 stream=None):
+        torch = _torch()
+        self.seg_off = _np(seg_off, np.int64)
+        self.pair_seg = _np(pair_seg, np.int32)
+        self.pair_pat = _np(pair_pat, np.int32)
+        self.patterns, self._blob, self._offs, self._lens = _pack_patterns(patterns)
+        self.plan = MergedPlan()
+        self._prep(None, 0, t, stream)
+        self.workspace = torch.empty(max(256, self.plan.workspace_bytes), dtype=torch.uint8, device=device)
+        self._prep(self.workspace.data_ptr(), self.workspace.numel(), t, stream)
+        self.counts = torch.zeros(max(1, self.pair_seg.size), dtype=torch.int64, device=device)
+
+    def _prep(self, ws, wsb, t, stream):
+        _check(lib.dfa_merged_prepare(self.seg_off.ctypes.data, self.seg_off.size - 1, self._blob.ctypes.data,
+                                      self._offs.ctypes.data, self._lens.ctypes.data, len(self.patterns),
+                                      self.pair_seg.ctypes.data, self.pair_pat.ctypes.data, self.pair_seg.size,
+                                      ws, wsb, _tune_ptr(t), ctypes.byref(self.plan), _stream_handle(stream)))
+
+    def run(self, text, stream=None):
+        """Enqueue the scan; counts land in self.counts (device int64)."""
+        _check(lib.dfa_merged_run(text.data_ptr() if text.numel() else None, text.numel(),
+                                  self.workspace.data_ptr(), ctypes.byref(self.plan), self.counts.data_ptr(),
+                                  _stream_handle(stream)))
+        return self.counts[:self.pair_seg.size]
+
+
+def count_merged(text, seg_off, patterns, pair_seg, pair_pat, t: Optional[Tune] = None,
+                 stream=None) -> np.ndarray:
+    """Per-pair occurrence counts with merged automata (synchronises)."""
+    b = MergedBatch(seg_off, patterns, pair_seg, pair_pat, t, device=text.device, stream=stream)
     return b.run(text, stream).cpu().numpy()
 
 

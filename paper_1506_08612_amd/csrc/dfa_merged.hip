@@ -1,0 +1,677 @@
+// Batched counting with merged multi-pattern automata for gfx950.
+//
+// The paper's improved Aho-Corasick automaton (Sec. "Implementation Aspects",
+// Fig. 4, Table 2) advances every pattern of a set with one table lookup per
+// text byte.  Here the pairs (segment, pattern) of each segment are merged
+// into as few automata as fit the LDS budget; one work item is (one tile of
+// a segment, one automaton); every lane walks its own span of the tile.
+//
+// Table layout.  The paper stores 256 columns per state so that a byte is its
+// own column.  With thousands of states per automaton that is 512 bytes per
+// state and no automaton worth merging fits LDS, so each automaton is kept as
+// a byte-class map (256 entries; every byte that occurs in none of its
+// patterns is one class, on which every state returns to the start) and a
+// 16-bit table with one column per class.  A step is two LDS reads: the
+// class of the byte (independent of the state, so off the dependent chain)
+// and the next state.  Reporting states are numbered last (first_final on),
+// so "is final" is one compare; visits of each reporting state are counted in
+// an LDS histogram and turned into per-pair counts at the end through the
+// per-state output lists.
+//
+// Ownership.  A walk owns the match starts of its span [w, w + S) and reads
+// max(m) - 1 bytes past it (clipped at the segment end).  A match that ends
+// inside the span starts inside it (the walk starts in the start state at w);
+// a match that ends in the overlap is counted only if it starts before w + S,
+// checked per reported pattern.  This start-position rule makes patterns of
+// unequal lengths exact, where a single m - 1 overlap (Sec. III.A) would count
+// some matches twice.
+//
+// Data movement is the single-pattern scan's: walks start on 128-byte
+// boundaries (the first walk of a segment may start before the segment and
+// skips the bytes in front of it), 64-byte rounds whose two halves of each
+// line are requested back to back, a wave-private LDS transpose, and the
+// overlap taken from the neighbouring walk's staged first round.  Items are
+// ordered so that consecutive items on one XCD walk the same tile with
+// different automata, which keeps the tile in that XCD's L2.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ac_build.h"
+#include "dfa.h"
+#include "dfa_internal.h"
+#include "launch_util.h"
+#include "walk_common.h"
+
+namespace {
+
+using namespace dfa_dev;
+
+constexpr int kLine = 64;                        // bytes of every walk staged per round
+constexpr int kXcds = 8;                         // workgroups are dealt to the XCDs in turn
+constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 128)
+constexpr int64_t kMaxSpan = 1024;
+constexpr int kDefaultWaves = 4;
+constexpr int kDefaultAutomatonBytes = 24 * 1024;
+constexpr int kMinAutomatonBytes = 4 * 1024;
+constexpr int kLdsPerCu = 160 * 1024;
+constexpr int kCmapBytes = 512;                  // 256 x u16: twice the class of each byte
+
+typedef __attribute__((address_space(3))) const uint16_t lds_u16;
+
+struct MAuto {
+    int64_t table_off;  // offset in the workspace: nstates x ncls u16 table (padded to 16 bytes), then the class map
+    int64_t fin_base;   // global index of this automaton's first reporting state
+    int32_t nstates;
+    int32_t first_final;
+    int32_t ncls;
+    int32_t maxm;
+    int32_t table_bytes;  // padded table bytes (the class map follows)
+    int32_t pad;
+};
+
+struct MItem {
+    int64_t tile_start;  // first byte of the tile's first walk
+    int64_t seg_lo;      // segment start: bytes before it are skipped
+    int64_t own_end;     // the tile owns match starts below this
+    int64_t seg_end;     // segment end: nothing is read past it
+    int32_t automaton;
+    int32_t span;        // S, a multiple of 128
+};
+
+struct OutEntry {
+    int32_t pair;
+    int32_t m;
+};
+
+struct MParams {
+    const uint8_t *text;
+    int64_t n;
+    const uint8_t *ws;  // workspace base (tables)
+    const MAuto *autos;
+    const MItem *items;
+    const int32_t *out_off;  // per global reporting state: its entries
+    const OutEntry *out_ent;
+    unsigned long long *visits;  // per global reporting state
+    unsigned long long *counts;  // per pair
+};
+
+// Per lane: bytes before the segment (skipped), owned starts, bytes that count.
+struct MLane {
+    uint32_t lo, own, len;
+};
+
+struct MCtx {
+    uint32_t row2;   // bytes per table row
+    uint32_t cmap;   // LDS address of the class map
+    uint32_t hist;   // LDS address of the visit counters
+    uint32_t F;      // first reporting state
+    int64_t fin_base;
+};
+
+// One automaton step: class of byte c (the map holds twice the class), then
+// the next state.
+__device__ __forceinline__ uint32_t mstep(uint32_t q, uint32_t c, const MCtx &x) {
+    const uint32_t k2 = *reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * c));
+    return *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2));
+}
+
+// A reporting state reached at byte j of the overlap: count each reported
+// pattern whose match starts inside the span (j - m + 1 < own).
+__device__ __forceinline__ void overlap_hit(const MParams &p, const MCtx &x, uint32_t q, uint32_t j, uint32_t own) {
+    const int64_t g = x.fin_base + int64_t(q - x.F);
+    const int32_t e1 = p.out_off[g + 1];
+    for (int32_t e = p.out_off[g]; e < e1; ++e) {
+        const OutEntry oe = p.out_ent[e];
+        if (j + 1 < own + uint32_t(oe.m)) atomicAdd(p.counts + oe.pair, 1ull);
+    }
+}
+
+// Walk 16 bytes; byte b of word w is byte jb + 4w + b of the walk.  Without
+// GUARD every byte is inside the lane's own span (full waves); with GUARD the
+// lane's [lo, own, len) decide.
+template <bool GUARD>
+__device__ __forceinline__ void mwalk16(const v4u &t, uint32_t &q, uint32_t jb, const MCtx &x, const MLane &L,
+                                        unsigned char *smem, const MParams &p) {
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t c = (t[w] >> (8 * b)) & 0xffu;
+            const uint32_t j = jb + uint32_t(4 * w + b);
+            q = mstep(q, c, x);
+            if (GUARD && j < L.lo) q = 0;  // in front of the segment: stay in the start state
+            if (q >= x.F) {
+                if (!GUARD || j < L.own)
+                    atomicAdd(hist + (q - x.F), 1u);
+                else if (j < L.len)
+                    overlap_hit(p, x, q, j, L.own);
+            }
+        }
+    }
+}
+
+// The four units of a staged round, the next one read from LDS while the
+// current one is walked.
+template <bool GUARD>
+__device__ __forceinline__ void mwalk_round(const v4u *xb, int lane, uint32_t &q, uint32_t rb, const MCtx &x,
+                                            const MLane &L, unsigned char *smem, const MParams &p) {
+    using G = Geo<kLine>;
+    v4u cur = unit_of<kLine>(xb, 0, lane, 0), nxt = cur;
+#pragma unroll
+    for (int u = 0; u < G::U; ++u) {
+        if (u + 1 < G::U) nxt = unit_of<kLine>(xb, 0, lane, u + 1);
+        mwalk16<GUARD>(cur, q, rb + 16u * u, x, L, smem, p);
+        cur = nxt;
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(512) void k_merged(MParams p) {
+    using G = Geo<kLine>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const MItem it = p.items[blockIdx.x];
+    const MAuto au = p.autos[it.automaton];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const uint32_t tb = uint32_t(__builtin_amdgcn_readfirstlane(au.table_bytes));
+    const uint32_t F = uint32_t(__builtin_amdgcn_readfirstlane(au.first_final));
+    const uint32_t nst = uint32_t(__builtin_amdgcn_readfirstlane(au.nstates));
+    const uint32_t nfin = nst - F;
+    const int maxm = __builtin_amdgcn_readfirstlane(au.maxm);
+
+    // LDS: table (from address 0), class map, visit counters, transpose buffers
+    MCtx x;
+    x.row2 = 2u * uint32_t(__builtin_amdgcn_readfirstlane(au.ncls));
+    x.cmap = tb;
+    x.hist = tb + kCmapBytes;
+    x.F = F;
+    x.fin_base = au.fin_base;
+    const uint32_t stage = (x.hist + 4u * nfin + 15u) & ~15u;
+    v4u *xb = reinterpret_cast<v4u *>(smem + stage + wave * (kWave * kLine));
+    {
+        const v4u *src = reinterpret_cast<const v4u *>(p.ws + au.table_off);
+        const uint32_t chunks = (tb + kCmapBytes) / 16u;
+        for (uint32_t i = threadIdx.x; i < chunks; i += blockDim.x) reinterpret_cast<v4u *>(smem)[i] = src[i];
+        uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
+        for (uint32_t i = threadIdx.x; i < nfin; i += blockDim.x) hist[i] = 0;
+    }
+    __syncthreads();
+
+    const int64_t S = it.span;
+    const int64_t wbase = it.tile_start + int64_t(wave) * kWave * S;
+    const int64_t wstart = wbase + int64_t(lane) * S;
+    MLane L;
+    {
+        int64_t lo = it.seg_lo - wstart, own = it.own_end - wstart;
+        lo = lo < 0 ? 0 : (lo > S ? S : lo);
+        own = own < 0 ? 0 : (own > S ? S : own);
+        int64_t len = 0;
+        if (own > lo) {
+            len = own + maxm - 1;
+            if (wstart + len > it.seg_end) len = it.seg_end - wstart;
+        }
+        L.lo = uint32_t(lo);
+        L.own = uint32_t(own);
+        L.len = uint32_t(len);
+    }
+    uint32_t q = 0;
+    const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(S) + 16u * uint32_t(lane % G::U);
+    const int rounds_all = int((S + maxm - 1 + kLine - 1) / kLine);
+    const int64_t wlast = wbase + int64_t(kWave - 1) * S;
+    const bool full = wbase >= it.seg_lo && wlast + S <= it.own_end && wlast + S + maxm - 1 <= it.seg_end &&
+                      wlast + int64_t(rounds_all) * kLine <= p.n;
+
+    if (full) {
+        // S is a multiple of 128: R is even and every round is whole
+        const int R = int(S / kLine);
+        const int rlast = R - 1;
+        const uint32_t off_none = 16u * uint32_t(lane % G::U);
+        const int hu = (maxm - 1 + 15) / 16;
+        v4u pa[1][G::U], pb[1][G::U], halo[1][H];
+        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 0, rlast);
+        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 1, rlast);
+        stage_round<1, kLine>(pa, xb, lane);
+        grab_halo<1, kLine, H>(halo, xb, lane, p.text, wbase, S, hu, G::U);
+        mwalk_round<false>(xb, lane, q, 0u, x, L, smem, p);
+        stage_round<1, kLine>(pb, xb, lane);
+        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 2, rlast);
+        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 3, rlast);
+        mwalk_round<false>(xb, lane, q, uint32_t(kLine), x, L, smem, p);
+        for (int r = 2; r < R; r += 2) {
+            stage_round<1, kLine>(pa, xb, lane);
+            mwalk_round<false>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
+            stage_round<1, kLine>(pb, xb, lane);
+            fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, r + 2, rlast);
+            fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
+            mwalk_round<false>(xb, lane, q, uint32_t((r + 1) * kLine), x, L, smem, p);
+        }
+        // the overlap: its first H units from registers, the rest from memory
+#pragma unroll
+        for (int u = 0; u < H; ++u)
+            if (u < hu) mwalk16<true>(halo[0][u], q, uint32_t(S) + 16u * u, x, L, smem, p);
+        for (int u = H; u < hu; ++u) {
+            const v4u t = *reinterpret_cast<const v4u *>(p.text + wstart + S + 16 * u);
+            mwalk16<true>(t, q, uint32_t(S) + 16u * u, x, L, smem, p);
+        }
+    } else {
+        // edge waves: the segment's first or last walks, or the text's end
+        v4u pf[1][G::U];
+        fetch_round<1, kLine, true>(pf, p.text, p.n, wbase, S, lane_off, 0);
+        for (int r = 0; r < rounds_all; ++r) {
+            stage_round<1, kLine>(pf, xb, lane);
+            if (r + 1 < rounds_all) fetch_round<1, kLine, true>(pf, p.text, p.n, wbase, S, lane_off, r + 1);
+            mwalk_round<true>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
+        }
+    }
+
+    // visit counters -> global, one atomic per nonzero counter
+    __syncthreads();
+    const uint32_t *hist = reinterpret_cast<const uint32_t *>(smem + x.hist);
+    for (uint32_t i = threadIdx.x; i < nfin; i += blockDim.x) {
+        const uint32_t v = hist[i];
+        if (v) atomicAdd(p.visits + au.fin_base + i, (unsigned long long)v);
+    }
+}
+
+__global__ void k_merged_zero(unsigned long long *counts, int64_t npairs, unsigned long long *visits, int64_t nfinal) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npairs + nfinal; i += stride) {
+        if (i < npairs)
+            counts[i] = 0;
+        else
+            visits[i - npairs] = 0;
+    }
+}
+
+// counts[pair] += visits of every reporting state that reports the pair's pattern
+__global__ void k_visits_to_counts(const unsigned long long *visits, const int32_t *out_off, const OutEntry *out_ent,
+                                   int64_t nfinal, unsigned long long *counts) {
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < nfinal;
+         g += int64_t(gridDim.x) * blockDim.x) {
+        const unsigned long long v = visits[g];
+        if (!v) continue;
+        for (int32_t e = out_off[g]; e < out_off[g + 1]; ++e) atomicAdd(counts + out_ent[e].pair, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+using dfa::hip_ok;
+
+const void *merged_fn(int H) {
+    if (H == 1) return reinterpret_cast<const void *>(&k_merged<1>);
+    return reinterpret_cast<const void *>(&k_merged<4>);
+}
+
+struct MHostPlan {
+    std::vector<MAuto> autos;
+    std::vector<MItem> items;
+    std::vector<int32_t> out_off{0};
+    std::vector<OutEntry> out_ent;
+    std::vector<uint8_t> area;  // tables and class maps
+    int waves = kDefaultWaves;
+    int H = 1;
+    int lds = 0;
+    int64_t text_bytes = 0;
+    int64_t nstates = 0;
+};
+
+int64_t auto_lds_bytes(const MAuto &a) {
+    return a.table_bytes + kCmapBytes + dfa::round_up(int64_t(a.nstates - a.first_final) * 4, 16);
+}
+
+int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const uint8_t *patterns,
+                  const int64_t *pat_off, const int32_t *pat_len, MHostPlan &hp) {
+    std::vector<const uint8_t *> pats;
+    std::vector<int32_t> lens;
+    int maxm = 0;
+    for (int64_t k : ks) {
+        const int32_t j = pair_pat[k];
+        pats.push_back(patterns + pat_off[j]);
+        lens.push_back(pat_len[j]);
+        maxm = std::max(maxm, int(pat_len[j]));
+    }
+    dfa::AcAutomaton a;
+    if (!dfa::ac_build(pats, lens, DFA_AC_MAX_STATES, a)) {
+        dfa::set_error("dfa_merged: an automaton would need more than %d states", DFA_AC_MAX_STATES);
+        return DFA_EINVAL;
+    }
+    MAuto m{};
+    m.nstates = a.nstates;
+    m.first_final = a.first_final;
+    m.ncls = a.ncls;
+    m.maxm = maxm;
+    m.table_bytes = int32_t(dfa::round_up(int64_t(a.nstates) * a.ncls * 2, 16));
+    m.table_off = int64_t(hp.area.size());
+    m.fin_base = int64_t(hp.out_off.size()) - 1;
+    hp.area.resize(hp.area.size() + size_t(m.table_bytes + kCmapBytes), 0);
+    uint16_t *tab = reinterpret_cast<uint16_t *>(hp.area.data() + m.table_off);
+    for (size_t i = 0; i < a.next.size(); ++i) tab[i] = uint16_t(a.next[i]);
+    uint16_t *cm = reinterpret_cast<uint16_t *>(hp.area.data() + m.table_off + m.table_bytes);
+    for (int b = 0; b < 256; ++b) cm[b] = uint16_t(2 * a.cls[b]);
+    for (int32_t f = 0; f < a.nstates - a.first_final; ++f) {
+        for (int32_t e = a.out_off[size_t(f)]; e < a.out_off[size_t(f) + 1]; ++e) {
+            const int64_t k = ks[size_t(a.out_pat[size_t(e)])];
+            hp.out_ent.push_back(OutEntry{int32_t(k), pat_len[pair_pat[k]]});
+        }
+        if (hp.out_ent.size() > size_t(0x7fffffff)) {
+            dfa::set_error("dfa_merged: too many output entries");
+            return DFA_EINVAL;
+        }
+        hp.out_off.push_back(int32_t(hp.out_ent.size()));
+    }
+    hp.nstates += a.nstates;
+    hp.autos.push_back(m);
+    return DFA_OK;
+}
+
+int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, const int64_t *pat_off,
+                const int32_t *pat_len, int32_t npat, const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
+                const dfa_tune *t, MHostPlan &hp) {
+    if (nseg < 0 || npat < 0 || npairs < 0 || (nseg > 0 && !seg_off) ||
+        (npat > 0 && (!patterns || !pat_off || !pat_len)) || (npairs > 0 && (!pair_seg || !pair_pat))) {
+        dfa::set_error("dfa_merged: bad counts or null arrays");
+        return DFA_EINVAL;
+    }
+    int budget = kDefaultAutomatonBytes;
+    int64_t fixed_span = 0;
+    if (t) {
+        for (int i = 0; i < 3; ++i)
+            if (t->reserved[i]) {
+                dfa::set_error("tune.reserved must be zero");
+                return DFA_EINVAL;
+            }
+        if (t->waves_per_group < 0 || t->waves_per_group > 8) {
+            dfa::set_error("tune.waves_per_group=%d outside [1, 8]", t->waves_per_group);
+            return DFA_EINVAL;
+        }
+        if (t->chain_bytes < 0 || t->chain_bytes % 128 || t->chain_bytes > (1 << 20)) {
+            dfa::set_error("tune.chain_bytes=%lld: merged scans take a multiple of 128 up to 2^20 (or 0)",
+                           (long long)t->chain_bytes);
+            return DFA_EINVAL;
+        }
+        if (t->automaton_bytes < 0 || (t->automaton_bytes && t->automaton_bytes < kMinAutomatonBytes)) {
+            dfa::set_error("tune.automaton_bytes=%d below %d", t->automaton_bytes, kMinAutomatonBytes);
+            return DFA_EINVAL;
+        }
+        if (t->waves_per_group) hp.waves = t->waves_per_group;
+        if (t->automaton_bytes) budget = t->automaton_bytes;
+        fixed_span = t->chain_bytes;
+    }
+    for (int32_t s = 0; s < nseg; ++s)
+        if (seg_off[s + 1] < seg_off[s] || seg_off[s] < 0) {
+            dfa::set_error("dfa_merged: seg_off must be nondecreasing and >= 0");
+            return DFA_EINVAL;
+        }
+    hp.text_bytes = nseg > 0 ? seg_off[nseg] : 0;
+    for (int32_t j = 0; j < npat; ++j)
+        if (pat_len[j] < 1 || pat_len[j] > DFA_MAX_M || pat_off[j] < 0) {
+            dfa::set_error("dfa_merged: pattern %d has length %d (1..%d) or offset %lld", j, pat_len[j], DFA_MAX_M,
+                           (long long)pat_off[j]);
+            return DFA_EINVAL;
+        }
+    std::vector<std::vector<int64_t>> by_seg(size_t(std::max(nseg, 0)));
+    for (int64_t k = 0; k < npairs; ++k) {
+        if (pair_seg[k] < 0 || pair_seg[k] >= nseg || pair_pat[k] < 0 || pair_pat[k] >= npat) {
+            dfa::set_error("dfa_merged: pair %lld refers to segment %d / pattern %d out of range", (long long)k,
+                           pair_seg[k], pair_pat[k]);
+            return DFA_EINVAL;
+        }
+        by_seg[size_t(pair_seg[k])].push_back(k);
+    }
+    std::vector<int32_t> order;
+    for (int32_t s = 0; s < nseg; ++s)
+        if (!by_seg[size_t(s)].empty() && seg_off[s + 1] > seg_off[s]) order.push_back(s);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return seg_off[a + 1] - seg_off[a] > seg_off[b + 1] - seg_off[b];
+    });
+    auto pat_less = [&](int64_t a, int64_t b) {
+        const int32_t ja = pair_pat[a], jb = pair_pat[b];
+        const int32_t n = std::min(pat_len[ja], pat_len[jb]);
+        const int c = std::memcmp(patterns + pat_off[ja], patterns + pat_off[jb], size_t(n));
+        return c ? c < 0 : pat_len[ja] < pat_len[jb];
+    };
+    // pass 1: the automata of every segment
+    int maxm_all = 1;
+    std::vector<std::pair<size_t, size_t>> seg_autos;  // [first, end) automata of order[i]
+    for (int32_t s : order) {
+        // this segment's pairs in pattern order, so that neighbours share prefixes
+        std::vector<int64_t> ks = by_seg[size_t(s)];
+        std::stable_sort(ks.begin(), ks.end(), pat_less);
+        bool used[256] = {};
+        for (int64_t k : ks) {
+            const int32_t j = pair_pat[k];
+            for (int32_t i = 0; i < pat_len[j]; ++i) used[patterns[pat_off[j] + i]] = true;
+        }
+        int ncls = 1;
+        for (int b = 0; b < 256; ++b) ncls += used[b];
+        // add patterns while the trie (counted incrementally from the common
+        // prefix with the previous pattern) fits the budget
+        const int64_t per_state = 2 * ncls + 4;
+        const size_t a_first = hp.autos.size();
+        std::vector<int64_t> cur;
+        int64_t states = 1;
+        for (int64_t k : ks) {
+            const int32_t j = pair_pat[k];
+            maxm_all = std::max(maxm_all, int(pat_len[j]));
+            int32_t common = 0;
+            if (!cur.empty()) {
+                const int32_t jp = pair_pat[cur.back()];
+                const int32_t n = std::min(pat_len[j], pat_len[jp]);
+                while (common < n && patterns[pat_off[j] + common] == patterns[pat_off[jp] + common]) ++common;
+            }
+            const int64_t add = pat_len[j] - common;
+            if (!cur.empty() && ((states + add) * per_state + kCmapBytes > budget || states + add > DFA_AC_MAX_STATES)) {
+                const int rc = add_automaton(cur, pair_pat, patterns, pat_off, pat_len, hp);
+                if (rc != DFA_OK) return rc;
+                cur.clear();
+                states = 1;
+            }
+            states += cur.empty() ? pat_len[j] : add;
+            cur.push_back(k);
+        }
+        if (!cur.empty()) {
+            const int rc = add_automaton(cur, pair_pat, patterns, pat_off, pat_len, hp);
+            if (rc != DFA_OK) return rc;
+        }
+        seg_autos.emplace_back(a_first, hp.autos.size());
+    }
+    hp.H = maxm_all <= 17 ? 1 : 4;
+    int64_t auto_max = 0;
+    for (const MAuto &a : hp.autos) auto_max = std::max(auto_max, auto_lds_bytes(a));
+    // fewer waves per workgroup if the largest automaton leaves too little room
+    while (hp.waves > 1 && auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) --hp.waves;
+    if (auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) {
+        dfa::set_error("dfa_merged: an automaton needs %lld bytes of LDS", (long long)auto_max);
+        return DFA_EINVAL;
+    }
+    // pass 2: work items, (tile, automaton), on the 128-byte grid of the text;
+    // short segments get short spans
+    const int64_t walks_per_tile = int64_t(hp.waves) * kWave;
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const int32_t s = order[oi];
+        const int64_t lo = seg_off[s], hi = seg_off[s + 1];
+        const int64_t a_first = int64_t(seg_autos[oi].first);
+        const int64_t na = int64_t(seg_autos[oi].second) - a_first;
+        const int64_t base = lo & ~int64_t(127);
+        const int64_t len = hi - base;
+        int64_t S = fixed_span;
+        if (!S) {
+            S = dfa::round_up(dfa::ceil_div(len, walks_per_tile), 128);
+            S = std::min(std::max(S, kMinSpan), kMaxSpan);
+        }
+        const int64_t tile = S * walks_per_tile;
+        const int64_t ntiles = dfa::ceil_div(len, tile);
+        for (int64_t tb = 0; tb < ntiles; tb += kXcds) {
+            const int64_t nt = std::min<int64_t>(kXcds, ntiles - tb);
+            for (int64_t a = 0; a < na; ++a)
+                for (int64_t ti = 0; ti < nt; ++ti) {
+                    MItem it{};
+                    it.tile_start = base + (tb + ti) * tile;
+                    it.seg_lo = lo;
+                    it.own_end = std::min(hi, it.tile_start + tile);
+                    it.seg_end = hi;
+                    it.automaton = int32_t(a_first + a);
+                    it.span = int32_t(S);
+                    hp.items.push_back(it);
+                }
+        }
+    }
+    if (hp.items.size() > size_t(0x7fffffff)) {
+        dfa::set_error("dfa_merged: too many work items");
+        return DFA_EINVAL;
+    }
+    hp.lds = int(auto_max + int64_t(hp.waves) * kWave * kLine);
+    return DFA_OK;
+}
+
+struct WsLayout {
+    int64_t autos = 0, items = 0, out_off = 0, out_ent = 0, visits = 0, area = 0, total = 0;
+};
+
+WsLayout ws_layout(const MHostPlan &hp) {
+    WsLayout L;
+    const int64_t nfin = int64_t(hp.out_off.size()) - 1;
+    L.autos = 0;
+    L.items = L.autos + dfa::round_up(int64_t(hp.autos.size() * sizeof(MAuto)), 256);
+    L.out_off = L.items + dfa::round_up(int64_t(hp.items.size() * sizeof(MItem)), 256);
+    L.out_ent = L.out_off + dfa::round_up(int64_t(hp.out_off.size() * sizeof(int32_t)), 256);
+    L.visits = L.out_ent + dfa::round_up(int64_t(hp.out_ent.size() * sizeof(OutEntry)), 256);
+    L.area = L.visits + dfa::round_up(nfin * 8, 256);
+    L.total = L.area + dfa::round_up(int64_t(hp.area.size()), 256);
+    return L;
+}
+
+}  // namespace
+
+extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns,
+                                  const int64_t *pat_off, const int32_t *pat_len, int32_t npat,
+                                  const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs, void *workspace,
+                                  int64_t workspace_bytes, const dfa_tune *tune, dfa_merged_plan *plan,
+                                  void *stream) {
+    if (!plan) {
+        dfa::set_error("dfa_merged_prepare: null plan");
+        return DFA_EINVAL;
+    }
+    MHostPlan hp;
+    int rc = plan_merged(seg_off, nseg, patterns, pat_off, pat_len, npat, pair_seg, pair_pat, npairs, tune, hp);
+    if (rc != DFA_OK) return rc;
+    // the automata's table offsets are relative to the area: make them workspace offsets
+    const WsLayout L = ws_layout(hp);
+    for (MAuto &a : hp.autos) a.table_off += L.area;
+    std::memset(plan, 0, sizeof(*plan));
+    plan->nitems = int64_t(hp.items.size());
+    plan->nautomata = int64_t(hp.autos.size());
+    plan->nstates = hp.nstates;
+    plan->nfinal = int64_t(hp.out_off.size()) - 1;
+    plan->npairs = npairs;
+    plan->text_bytes = hp.text_bytes;
+    plan->workspace_bytes = L.total;
+    plan->items_offset = L.items;
+    plan->outputs_offset = L.out_off;
+    plan->entries_offset = L.out_ent;
+    plan->visits_offset = L.visits;
+    plan->waves_per_group = hp.waves;
+    plan->lds_bytes = hp.lds;
+    plan->reserved[0] = hp.H;
+    if (!workspace) {
+        dfa::clear_error();
+        return DFA_OK;  // size query
+    }
+    if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        dfa::set_error("dfa_merged_prepare: workspace of %lld bytes (256-aligned) needed, got %lld",
+                       (long long)L.total, (long long)workspace_bytes);
+        return DFA_ENOSPACE;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
+    struct Part {
+        int64_t off;
+        const void *src;
+        size_t bytes;
+    } parts[] = {
+        {L.autos, hp.autos.data(), hp.autos.size() * sizeof(MAuto)},
+        {L.items, hp.items.data(), hp.items.size() * sizeof(MItem)},
+        {L.out_off, hp.out_off.data(), hp.out_off.size() * sizeof(int32_t)},
+        {L.out_ent, hp.out_ent.data(), hp.out_ent.size() * sizeof(OutEntry)},
+        {L.area, hp.area.data(), hp.area.size()},
+    };
+    for (const Part &pt : parts)
+        if (pt.bytes && !hip_ok(hipMemcpyAsync(ws + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, st),
+                                "merged plan upload"))
+            return DFA_EHIP;
+    // the host arrays are freed on return: make sure the copies are done
+    if (!hip_ok(hipStreamSynchronize(st), "merged plan upload")) return DFA_EHIP;
+    dfa::clear_error();
+    return DFA_OK;
+}
+
+extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, const dfa_merged_plan *plan,
+                              int64_t *counts, void *stream) {
+    if (!plan || n < 0 || (!text && n > 0) || (plan->npairs > 0 && !counts) || (plan->nitems > 0 && !workspace)) {
+        dfa::set_error("dfa_merged_run: null argument or n < 0");
+        return DFA_EINVAL;
+    }
+    if (plan->text_bytes > n) {
+        dfa::set_error("dfa_merged_run: segments span %lld bytes, text has %lld", (long long)plan->text_bytes,
+                       (long long)n);
+        return DFA_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(text) & 15) || (reinterpret_cast<uintptr_t>(counts) & 7) ||
+        (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        dfa::set_error("dfa_merged_run: text must be 16-byte, counts 8-byte, workspace 256-byte aligned");
+        return DFA_EINVAL;
+    }
+    const int H = plan->reserved[0];
+    if ((H != 1 && H != 4) || plan->waves_per_group < 1 || plan->waves_per_group > 8 || plan->lds_bytes < 0 ||
+        plan->lds_bytes > kLdsPerCu) {
+        dfa::set_error("dfa_merged_run: plan not made by dfa_merged_prepare");
+        return DFA_EINVAL;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
+    unsigned long long *visits = reinterpret_cast<unsigned long long *>(ws + plan->visits_offset);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counts);
+    if (plan->npairs + plan->nfinal > 0) {
+        const int64_t want = dfa::ceil_div(plan->npairs + plan->nfinal, 256);
+        hipLaunchKernelGGL(k_merged_zero, dim3(unsigned(std::min<int64_t>(want, 4096))), dim3(256), 0, st, cnt,
+                           plan->npairs, visits, plan->nfinal);
+        if (!hip_ok(hipGetLastError(), "k_merged_zero launch")) return DFA_EHIP;
+    }
+    if (plan->nitems == 0) {
+        dfa::clear_error();
+        return DFA_OK;
+    }
+    const void *fn = merged_fn(H);
+    if (!dfa::allow_lds(fn, kLdsPerCu)) return DFA_EHIP;
+    MParams mp{};
+    mp.text = text;
+    mp.n = n;
+    mp.ws = ws;
+    mp.autos = reinterpret_cast<const MAuto *>(ws);
+    mp.items = reinterpret_cast<const MItem *>(ws + plan->items_offset);
+    mp.out_off = reinterpret_cast<const int32_t *>(ws + plan->outputs_offset);
+    mp.out_ent = reinterpret_cast<const OutEntry *>(ws + plan->entries_offset);
+    mp.visits = visits;
+    mp.counts = cnt;
+    void *args[] = {&mp};
+    if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(plan->nitems)), dim3(plan->waves_per_group * kWave), args,
+                                size_t(plan->lds_bytes), st),
+                "k_merged launch"))
+        return DFA_EHIP;
+    if (plan->nfinal > 0) {
+        const int64_t want = dfa::ceil_div(plan->nfinal, 256);
+        hipLaunchKernelGGL(k_visits_to_counts, dim3(unsigned(std::min<int64_t>(want, 4096))), dim3(256), 0, st, visits,
+                           mp.out_off, mp.out_ent, plan->nfinal, cnt);
+        if (!hip_ok(hipGetLastError(), "k_visits_to_counts launch")) return DFA_EHIP;
+    }
+    dfa::clear_error();
+    return DFA_OK;
+}

@@ -176,46 +176,6 @@ __device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q
 // registers free (one more wave per SIMD).
 constexpr int halo_units_for(int m) { return m <= 17 ? 1 : 4; }
 
-// The first H units of the overlap of each of the lane's walks, taken right
-// after round 0 is staged: the overlap of walk (slot s, lane l) is the start
-// of walk (s, l + 1), row s * 64 + l + 1 of the wave's buffer.  The last walk
-// of the wave (whose neighbour is another wave's) and units past the ones the
-// buffer holds (`valid` < H only for spans shorter than a round) are loaded
-// from memory, with u clamped to hu - 1 so that every address stays inside
-// the overlap.
-template <int K, int LINE, int H>
-__device__ __forceinline__ void grab_halo(v4u (&h)[K][H], const v4u *xb, int lane, const uint8_t *text, int64_t g0,
-                                          int64_t S, int hu, int valid) {
-    using G = Geo<LINE>;
-    const int last = hu > 0 ? hu - 1 : 0;
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int rho = s * kWave + lane + 1;
-        const bool in_buf = rho < K * kWave;
-        const int rr = in_buf ? rho : K * kWave - 1;
-        const int row = rr % kWave;
-#pragma unroll
-        for (int u = 0; u < H; ++u) {
-            v4u v = xb[rr * G::U + (u ^ G::swz(row))];
-            if (hu > 0 && (!in_buf || u >= valid))
-                v = *reinterpret_cast<const v4u *>(text + (g0 + s * kWave + lane + 1) * S + 16 * (u < last ? u : last));
-            h[s][u] = v;
-        }
-    }
-}
-
-// Round r of the wave's walks (in-bounds path): rounds before the last use the
-// lane's own unit offset, the last one the clamped offset; r past the last
-// round loads the text's first line (a cache hit whose values are never used).
-template <int K, int LINE>
-__device__ __forceinline__ void fetch_round_or_none(v4u (&pf)[K][Geo<LINE>::U], const uint8_t *text, int64_t wb,
-                                                    int64_t S, uint32_t off, uint32_t off_last, uint32_t off_none,
-                                                    int r, int rlast) {
-    const bool real = r <= rlast;  // wave-uniform
-    fetch_round<K, LINE, false>(pf, text, 0, real ? wb : 0, real ? S : 0,
-                                r < rlast ? off : (real ? off_last : off_none), real ? r : 0);
-}
-
 template <int K, int LINE, int MODE, int H>
 __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     using G = Geo<LINE>;
@@ -313,7 +273,7 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
         v4u halo[K][H];
         // round 0 (and 1), then the steady state from round 2
         stage_round<K, LINE>(pa, xb, lane);
-        grab_halo<K, LINE, H>(halo, xb, lane, p.text, g0, p.S, hu, rlast == 0 ? int(ulast) : G::U);
+        grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
         if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
         walk_round<K, LINE, MODE, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
         if (rlast >= 1) {
@@ -560,7 +520,7 @@ bool check_tune(const dfa_tune *t) {
                        "(1 with 64 or 128, 2 with 64)", t->chains_per_lane, line);
         return false;
     }
-    if (t->dfas_per_group < 0 || t->tile_bytes < 0) {
+    if (t->dfas_per_group < 0 || t->automaton_bytes < 0) {
         dfa::set_error("tune: negative field");
         return false;
     }
