@@ -15,11 +15,12 @@ Also reported:
   prefix of the same text for the same five patterns;
 * per-pattern latency p50/p99 of the full call over the timed steps;
 * batched -- 1 GB GC-41% text x 1024 patterns (lengths 4..64, half drawn from
-  the text) in one batched launch (autotuned shape, replayed from a HIP graph)
-  against the same GPU running one count-only launch per pattern, in
-  pattern-bytes/s;
+  the text) with merged multi-pattern automata in one launch (autotuned
+  automaton budget and shape, replayed from a HIP graph) against the same GPU
+  running one count-only launch per pattern, in pattern-bytes/s; the batched
+  scan with one automaton per pattern is timed beside it;
 * segmented -- 2000 contig-like segments (log-normal lengths, median 200 kB,
-  ~2 GB, 2% 'N' runs), 1..16 patterns each, one batched launch;
+  ~2 GB, 2% 'N' runs), 1..16 patterns each, one merged launch;
 * serving -- Poisson arrivals of (text, patterns) queries (text log-uniform in
   [10 kB, 500 MB], 1..64 patterns of length 4..64) at 80% of the capacity the
   server sustains in a closed loop; p50/p99 latency (arrival to counts on the
@@ -46,7 +47,7 @@ sys.path.insert(0, ROOT)
 METRIC = "text GB/s (and % of HBM peak) single-pattern; pattern-bytes/s batched; p50/p99"
 HBM_PEAK_GBS = 8000.0
 PATTERN_LENGTHS = (4, 8, 16, 32, 64)
-SCAN_SOURCE = os.path.join(ROOT, "paper_1506_08612_amd", "csrc", "dfa_scan.hip")
+SCAN_SOURCES = [os.path.join(ROOT, "paper_1506_08612_amd", "csrc", f) for f in ("dfa_scan.hip", "walk_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_count_genome3200MB_traffic.txt")
 
 
@@ -54,8 +55,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -67,7 +71,7 @@ def read_traffic():
             if ":" in ln and not ln.startswith("#"):
                 k, v = ln.split(":", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("kernel_source_sha256_16") != source_hash(SCAN_SOURCE):
+        if kv.get("kernel_source_sha256_16") != source_hash(SCAN_SOURCES):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -104,6 +108,7 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
     ps = api.PatternSet(w.patterns)
     out = torch.empty(npat, dtype=torch.int64, device=d.device)
     tabs = [ps.tables[int(o):int(o) + (int(mm) + 1) * 256] for o, mm in zip(ps.table_off, ps.m)]
+    pair_seg, pair_pat = np.zeros(npat, np.int64), np.arange(npat)
 
     def one_per_launch():
         for j in range(npat):
@@ -111,20 +116,28 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
 
     base_ms = _events_ms(torch, one_per_launch, 1)
     ref = out.cpu().numpy()
-    pairs = (np.zeros(npat, np.int64), np.arange(npat))
-    t, entry = autotune.tune_batch(d, [0, n], ps, *pairs, reps=1)
-    b = api.Batch([0, n], ps, *pairs, t)
+    # merged multi-pattern automata: autotuned, captured in a HIP graph
+    t, entry = autotune.tune_merged(d, [0, n], w.patterns, pair_seg, pair_pat, reps=2)
+    b = api.MergedBatch([0, n], w.patterns, pair_seg, pair_pat, t, device=d.device)
     g = graph.GraphedBatch(d, b)
-    ms = _events_ms(torch, g.replay, 3)
+    ms = _events_ms(torch, g.replay, 5)
     equal = bool(np.array_equal(b.counts.cpu().numpy()[:npat], ref))
+    # one automaton per pattern (256-column tables), groups of automata per workgroup
+    sb = api.Batch([0, n], ps, pair_seg, pair_pat)
+    sep_ms = _events_ms(torch, lambda: sb.run(d), 1)
+    sep_equal = bool(np.array_equal(sb.counts.cpu().numpy()[:npat], ref))
     pb = n * npat
-    return {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), counts only",
+    return {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), per-pattern counts",
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1),
             "one_per_launch_pattern_bytes_per_s": round(pb / (base_ms * 1e-3), 1),
-            "speedup_vs_one_per_launch": round(base_ms / ms, 3),
+            "speedup_vs_one_per_launch": round(base_ms / ms, 2),
             "ms": round(ms, 3), "one_per_launch_ms": round(base_ms, 3),
-            "tune": entry["tune"], "groups": int(b.plan.ngroups), "items": int(b.plan.nitems),
-            "counts_equal_one_per_launch": equal}
+            "method": "merged multi-pattern automata (class-compressed 16-bit tables), HIP graph replay",
+            "tune": entry["tune"], "automata": int(b.plan.nautomata), "states": int(b.plan.nstates),
+            "items": int(b.plan.nitems), "counts_equal_one_per_launch": equal,
+            "separate_automata": {"ms": round(sep_ms, 3), "pattern_bytes_per_s": round(pb / (sep_ms * 1e-3), 1),
+                                  "speedup_vs_one_per_launch": round(base_ms / sep_ms, 2),
+                                  "counts_equal_one_per_launch": sep_equal}}
 
 
 def bench_segmented(torch, api, synth):
@@ -132,15 +145,19 @@ def bench_segmented(torch, api, synth):
     log("segmented: 2000 contig-like segments")
     w = synth.uneven_segments()
     d = api.to_device(w.text)
-    ps = api.PatternSet(w.patterns)
-    b = api.Batch(w.seg_off, ps, w.pair_seg, w.pair_pat)
+    b = api.MergedBatch(w.seg_off, w.patterns, w.pair_seg, w.pair_pat, device=d.device)
     g = graph.GraphedBatch(d, b)
-    ms = _events_ms(torch, g.replay, 3)
+    ms = _events_ms(torch, g.replay, 5)
+    sb = api.Batch(w.seg_off, api.PatternSet(w.patterns), w.pair_seg, w.pair_pat)
+    sep_ms = _events_ms(torch, lambda: sb.run(d), 3)
+    equal = bool(np.array_equal(b.counts.cpu().numpy(), sb.counts.cpu().numpy()))
     seg_len = np.diff(w.seg_off)
     pb = int(seg_len[w.pair_seg].sum())
     return {"workload": f"{seg_len.size} segments, {int(w.seg_off[-1])} B, {w.pair_seg.size} (segment, pattern) pairs",
             "ms": round(ms, 3), "text_GBps": round(int(w.seg_off[-1]) / ms / 1e6, 1),
-            "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems)}
+            "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems),
+            "method": "merged automata per segment, HIP graph replay",
+            "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal}
 
 
 def bench_serving(torch, nq):
@@ -183,6 +200,8 @@ def main(argv=None) -> int:
     ap.add_argument("--skip-extra", action="store_true",
                     help="skip the batched, segmented and serving measurements")
     ap.add_argument("--serve-queries", type=int, default=64)
+    ap.add_argument("--only", choices=("batched", "segmented", "serving"),
+                    help="run only this leg and print its figures (for profiling)")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -195,6 +214,12 @@ def main(argv=None) -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.only:
+        legs = {"batched": lambda: bench_batched(torch, api, synth),
+                "segmented": lambda: bench_segmented(torch, api, synth),
+                "serving": lambda: bench_serving(torch, a.serve_queries)}
+        print(json.dumps({a.only: legs[a.only]()}), flush=True)
+        return 0
     stream = torch.cuda.current_stream()
 
     log(f"generating genome-like text n={a.n}")

@@ -37,6 +37,14 @@ BATCH_CANDIDATES: List[Dict[str, int]] = [
     dict(dfas_per_group=4, waves_per_group=4),
 ]
 
+MERGED_CANDIDATES: List[Dict[str, int]] = [
+    dict(),  # library default (48 KiB automata, 8 waves)
+    dict(automaton_bytes=24 * 1024, waves_per_group=8),
+    dict(automaton_bytes=96 * 1024, waves_per_group=8),
+    dict(automaton_bytes=48 * 1024, waves_per_group=4),
+    dict(automaton_bytes=48 * 1024, waves_per_group=8, chain_bytes=512),
+]
+
 _lock = threading.Lock()
 
 
@@ -147,3 +155,23 @@ def tune_batch(text, seg_off, pset: "api.PatternSet", pair_seg, pair_pat, reps: 
         batches[k].run(text)
 
     return _pick(key, candidates or BATCH_CANDIDATES, run_one, reps, force)
+
+
+def tune_merged(text, seg_off, patterns, pair_seg, pair_pat, reps: int = 2, force: bool = False,
+                candidates: Optional[Iterable[Dict[str, int]]] = None):
+    """Fastest automaton budget and launch shape for a merged batched scan of this
+    workload class."""
+    import numpy as np
+    so = np.asarray(seg_off, dtype=np.int64)
+    lens = [len(p) for p in patterns]
+    key = "merged|" + batch_class(int(so[-1] - so[0]), len(patterns), float(np.mean(lens)) if lens else 0.0,
+                                  so.size - 1)
+    built = {}
+
+    def run_one(t):
+        k = (t.automaton_bytes, t.waves_per_group, t.chain_bytes)
+        if k not in built:
+            built[k] = api.MergedBatch(so, patterns, pair_seg, pair_pat, t, device=text.device)
+        built[k].run(text)
+
+    return _pick(key, candidates or MERGED_CANDIDATES, run_one, reps, force)

@@ -54,8 +54,8 @@ constexpr int kLine = 64;                        // bytes of every walk staged p
 constexpr int kXcds = 8;                         // workgroups are dealt to the XCDs in turn
 constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 128)
 constexpr int64_t kMaxSpan = 1024;
-constexpr int kDefaultWaves = 4;
-constexpr int kDefaultAutomatonBytes = 24 * 1024;
+constexpr int kDefaultWaves = 8;
+constexpr int kDefaultAutomatonBytes = 48 * 1024;
 constexpr int kMinAutomatonBytes = 4 * 1024;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kCmapBytes = 512;                  // 256 x u16: twice the class of each byte

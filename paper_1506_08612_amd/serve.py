@@ -10,7 +10,8 @@ of every pattern in the text.  The server
   batches run on the compute stream;
 * fuses every admitted request whose upload has been issued into ONE batched
   scan launch: each request's text is a segment of the arena (gaps between
-  texts are segments nobody asks about), each (request, pattern) is a pair;
+  texts are segments nobody asks about), each (request, pattern) is a pair,
+  and the patterns of each request are merged into multi-pattern automata;
 * keeps at most `max_inflight` fused launches on the device; requests that
   arrive while others run are admitted as slots and memory free up and join
   the next launch, so their work overlaps on the device;
@@ -19,8 +20,8 @@ of every pattern in the text.  The server
 `mode="fifo"` is the one-query-per-launch baseline on the same trace: one
 request at a time, upload, plan, launch, wait.
 
-Everything device-side is the library's batched scan (dfa_batch_prepare /
-dfa_batch_run); this module only schedules.
+Everything device-side is the library's merged batched scan
+(dfa_merged_prepare / dfa_merged_run); this module only schedules.
 """
 from __future__ import annotations
 
@@ -114,7 +115,7 @@ class Result:
 
 
 class _Job:
-    __slots__ = ("req", "pinned", "offset", "tables", "admitted", "copied", "launched")
+    __slots__ = ("req", "pinned", "offset", "admitted", "copied", "launched")
 
 
 class Server:
@@ -135,54 +136,42 @@ class Server:
         t = self.torch.from_numpy(np.ascontiguousarray(req.text, dtype=np.uint8))
         return t.pin_memory() if t.numel() else t
 
-    def _tables(self, req: Request):
-        return [api.build_table(p) for p in req.patterns]
-
     def _launch(self, jobs: List[_Job], now):
-        """One fused batched scan over the jobs' texts; returns (event, counts tensor, spans)."""
+        """One fused merged-automaton scan over the jobs' texts; returns (event, counts
+        tensor, spans, buffers to keep alive until the event has fired)."""
         torch = self.torch
         placed = [(j.offset, j.req.text.size) for j in jobs]
         seg_off, seg_of = segments_for(placed, self.arena_bytes)
-        blobs, m, pair_seg, pair_pat, spans = [], [], [], [], []
-        toff = 0
-        table_off = []
+        pats, pair_seg, spans = [], [], []
         for ji, j in enumerate(jobs):
             first = len(pair_seg)
-            for p, tab in zip(j.req.patterns, j.tables):
-                blobs.append(tab.reshape(-1))
-                table_off.append(toff)
-                toff += tab.size
-                m.append(len(p))
+            for p in j.req.patterns:
+                pats.append(p)
                 pair_seg.append(seg_of[ji])
-                pair_pat.append(len(pair_pat))
             spans.append((first, len(pair_seg)))
-        blob = np.concatenate(blobs) if blobs else np.zeros(256, np.uint8)
-        with torch.cuda.stream(self.copy_stream):
-            tables = torch.from_numpy(blob).pin_memory().to(self.device, non_blocking=True)
+        _, blob, offs, lens = api._pack_patterns(pats)
         so = np.ascontiguousarray(seg_off)
-        toff_a = np.array(table_off, np.int64)
-        m_a = np.array(m, np.int32)
         ps_a = np.array(pair_seg, np.int32)
-        pp_a = np.array(pair_pat, np.int32)
-        plan = api.BatchPlan()
-        api._check(api.lib.dfa_batch_prepare(so.ctypes.data, so.size - 1, toff_a.ctypes.data, m_a.ctypes.data,
-                                             m_a.size, ps_a.ctypes.data, pp_a.ctypes.data, ps_a.size, None, 0,
-                                             api._tune_ptr(self.tune), api.ctypes.byref(plan), None))
-        ws = torch.empty(max(1, plan.workspace_bytes), dtype=torch.uint8, device=self.device)
-        # the plan upload synchronises the copy stream (texts and tables are on it too)
-        api._check(api.lib.dfa_batch_prepare(so.ctypes.data, so.size - 1, toff_a.ctypes.data, m_a.ctypes.data,
-                                             m_a.size, ps_a.ctypes.data, pp_a.ctypes.data, ps_a.size,
-                                             ws.data_ptr(), ws.numel(), api._tune_ptr(self.tune),
-                                             api.ctypes.byref(plan), self.copy_stream.cuda_stream))
+        pp_a = np.arange(len(pats), dtype=np.int32)
+        plan = api.MergedPlan()
+
+        def prepare(ws, wsb, stream):
+            api._check(api.lib.dfa_merged_prepare(so.ctypes.data, so.size - 1, blob.ctypes.data, offs.ctypes.data,
+                                                  lens.ctypes.data, len(pats), ps_a.ctypes.data, pp_a.ctypes.data,
+                                                  ps_a.size, ws, wsb, api._tune_ptr(self.tune),
+                                                  api.ctypes.byref(plan), stream))
+
+        prepare(None, 0, None)
+        ws = torch.empty(max(256, plan.workspace_bytes), dtype=torch.uint8, device=self.device)
+        # the plan upload synchronises the copy stream, where the texts were uploaded too
+        prepare(ws.data_ptr(), ws.numel(), self.copy_stream.cuda_stream)
         counts = torch.empty(max(1, ps_a.size), dtype=torch.int64, device=self.device)
         self.compute_stream.wait_stream(self.copy_stream)
-        api._check(api.lib.dfa_batch_run(self.arena_buf.data_ptr(), self.arena_bytes, tables.data_ptr(),
-                                         tables.numel(), ws.data_ptr(), api.ctypes.byref(plan),
-                                         counts.data_ptr(), self.compute_stream.cuda_stream))
+        api._check(api.lib.dfa_merged_run(self.arena_buf.data_ptr(), self.arena_bytes, ws.data_ptr(),
+                                          api.ctypes.byref(plan), counts.data_ptr(), self.compute_stream.cuda_stream))
         ev = torch.cuda.Event()
         ev.record(self.compute_stream)
-        # keep the per-launch buffers alive until the event has fired
-        return ev, counts, spans, (tables, ws)
+        return ev, counts, spans, (ws,)
 
     # -- the loop -------------------------------------------------------------------------
     def serve(self, trace: List[Request], mode: str = "continuous", time_scale: float = 1.0) -> List[Result]:
@@ -195,7 +184,6 @@ class Server:
             if r.text.size > self.arena_bytes:
                 raise ValueError(f"request {r.qid}: text of {r.text.size} bytes exceeds the arena")
         pinned = {r.qid: self._pin(r) for r in reqs}
-        tables = {r.qid: self._tables(r) for r in reqs}
         arena = Arena(self.arena_bytes)
         pending: List[Request] = []
         admitted: List[_Job] = []
@@ -233,7 +221,7 @@ class Server:
                     break
                 pending.pop(0)
                 j = _Job()
-                j.req, j.pinned, j.offset, j.tables = r, pinned[r.qid], off, tables[r.qid]
+                j.req, j.pinned, j.offset = r, pinned[r.qid], off
                 j.admitted = clock()
                 if r.text.size:
                     with torch.cuda.stream(self.copy_stream):
