@@ -21,11 +21,12 @@ Also reported:
   scan with one automaton per pattern is timed beside it;
 * segmented -- 2000 contig-like segments (log-normal lengths, median 200 kB,
   ~2 GB, 2% 'N' runs), 1..16 patterns each, one merged launch;
-* serving -- Poisson arrivals of (text, patterns) queries (text log-uniform in
-  [10 kB, 500 MB], 1..64 patterns of length 4..64) at 80% of the capacity the
-  server sustains in a closed loop; p50/p99 latency (arrival to counts on the
-  host, upload included) and text GB/s, against the one-query-per-launch FIFO
-  form on the same trace.
+* serving -- 1000 Poisson arrivals (after 50 warm-up queries) of (text,
+  patterns) queries (text log-uniform in [10 kB, 500 MB] drawn from a pool of
+  64 texts, 1..64 patterns of length 4..64) at 80% of the capacity the server
+  sustains in a closed loop; p50/p99 latency (arrival to counts on the host,
+  upload included) and text GB/s, against the one-query-per-launch FIFO form on
+  the same trace.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -160,26 +161,30 @@ def bench_segmented(torch, api, synth):
             "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal}
 
 
-def bench_serving(torch, nq):
+def bench_serving(torch, nq, warm=50, pool=64):
     from paper_1506_08612_amd import serve
-    log(f"serving: {nq} queries")
-    trace = serve.make_trace(nq, rate_hz=1.0, seed=5)
+    log(f"serving: {warm} warm-up + {nq} measured queries (texts from a pool of {pool})")
+    trace = serve.make_trace(warm + nq, rate_hz=1.0, seed=5, pool=pool)
     srv = serve.Server(arena_bytes=8 << 30)
-    srv.serve(trace[:4], mode="continuous")  # warm up
-    closed = [serve.Request(r.qid, r.text, r.patterns, 0.0) for r in trace]
+    srv.serve([serve.Request(r.qid, r.text, r.patterns, 0.0) for r in trace[:warm]], mode="continuous")
+    meas = trace[warm:]
+    closed = [serve.Request(r.qid, r.text, r.patterns, 0.0) for r in meas]
     cap = srv.serve(closed, mode="continuous")
-    makespan = max(r.done for r in cap)
-    capacity = nq / makespan
+    capacity = nq / max(r.done for r in cap)
     rate = 0.8 * capacity
     # the seeded Poisson trace has rate 1/s: dividing its arrival times by `rate` rescales it
-    timed = [serve.Request(r.qid, r.text, r.patterns, r.arrival / rate) for r in trace]
+    t_first = meas[0].arrival
+    timed = [serve.Request(r.qid, r.text, r.patterns, (r.arrival - t_first) / rate) for r in meas]
     res = srv.serve(timed, mode="continuous")
     cont = serve.summarize(res)
     fifo_res = srv.serve(timed, mode="fifo")
     fifo = serve.summarize(fifo_res)
     same = all(np.array_equal(x.counts, y.counts) for x, y in zip(res, fifo_res))
-    return {"workload": f"{nq} queries, text log-uniform [1e4, 5e8] B (2% N runs), 1..64 patterns m=U[4,64], "
+    total = sum(r.text.size for r in meas)
+    return {"workload": f"{nq} queries after {warm} warm-up, text log-uniform [1e4, 5e8] B (2% N runs; "
+                        f"{pool} distinct texts, each query uploads its own copy), 1..64 patterns m=U[4,64], "
                         f"Poisson arrivals at 0.8 x closed-loop capacity",
+            "text_bytes": int(total),
             "capacity_qps": round(capacity, 2), "rate_qps": round(rate, 2),
             "continuous": cont, "one_query_per_launch": fifo,
             "answers_equal_across_modes": bool(same)}
@@ -199,7 +204,7 @@ def main(argv=None) -> int:
                     help="also run one device copy of this many bytes (counter calibration)")
     ap.add_argument("--skip-extra", action="store_true",
                     help="skip the batched, segmented and serving measurements")
-    ap.add_argument("--serve-queries", type=int, default=64)
+    ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--only", choices=("batched", "segmented", "serving"),
                     help="run only this leg and print its figures (for profiling)")
     a = ap.parse_args(argv)

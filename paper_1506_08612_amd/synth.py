@@ -266,9 +266,9 @@ def query_trace(nq: int, rate_hz: float, seed: int = 5, len_lo: float = 1e4, len
     return out
 
 
-def query_text(q: Query, n_frac: float = 0.02, n_run_mean: float = 5000):
-    """Materialise one query: its text and its patterns (half drawn, half random)."""
-    text = genome_like(q.text_len, q.seed, n_frac, n_run_mean)
+def query_patterns(text: np.ndarray, q: Query) -> list:
+    """The query's patterns over `text`: lengths q.pattern_lens, every other one drawn from the
+    text, the rest (and any that finds no pure-ACGT window) random."""
     rng = np.random.default_rng([q.seed, 0x5150])
     pats = []
     for i, m in enumerate(q.pattern_lens):
@@ -278,4 +278,10 @@ def query_text(q: Query, n_frac: float = 0.02, n_run_mean: float = 5000):
         if p is None:
             p = random_pattern(m, rng)
         pats.append(p)
-    return text, pats
+    return pats
+
+
+def query_text(q: Query, n_frac: float = 0.02, n_run_mean: float = 5000):
+    """Materialise one query: its text and its patterns (half drawn, half random)."""
+    text = genome_like(q.text_len, q.seed, n_frac, n_run_mean)
+    return text, query_patterns(text, q)
