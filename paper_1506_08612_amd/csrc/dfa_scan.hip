@@ -67,9 +67,9 @@ struct ScanParams {
     int64_t cap;
 };
 
-// matches per walk whose positions the counting pass keeps; walks with more
-// are walked again by the positions pass
-constexpr int kBuffered = 2;
+// matches per walk whose end offsets the counting pass keeps (in the
+// workspace); walks with more are walked again by the positions pass
+constexpr int kBuffered = 16;
 
 __host__ __device__ inline int table_lds_bytes(int m) { return table_lds_rows_bytes(m + 1); }
 
@@ -77,16 +77,26 @@ struct WalkLane {
     int64_t wstart;  // first byte of the walk
     uint32_t len;    // bytes the walk reads (span + m - 1, clipped at the text end)
     uint32_t cnt;    // matches (per-walk counting pass)
-    uint32_t buf[kBuffered];
+    uint32_t *buf;   // its kBuffered end offsets (per-walk counting pass)
     int64_t off;     // next output slot (positions pass)
 };
 
+// The end offsets of a lane's matches in one unit (hit mask from walk16_hits,
+// first byte in bit 15), in increasing order, into the walk's buffer.
+__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, WalkLane &w) {
+    while (hm) {
+        const int b = 31 - __clz(hm);
+        if (w.cnt < uint32_t(kBuffered)) w.buf[w.cnt] = jb + uint32_t(15 - b);
+        ++w.cnt;
+        hm ^= 1u << b;
+    }
+}
+
 // Walk 16 bytes: byte b of word w is byte jb + 4w + b of the walk.  GUARD:
 // only bytes below the walk's length count.  kCount: ballot + scalar count.
-// kCountPerWalk: the same, and when the wave's count moved (rare unless the
-// pattern is short) the unit is walked again from its start state to count
-// per walk and keep the first kBuffered match ends.  kPositions: write the
-// start offset of every match.
+// kCountPerWalk: per-walk count and the first kBuffered match ends (the
+// total is summed from the per-walk counts at the end).  kPositions: write
+// the start offset of every match.
 template <int K, int MODE, bool GUARD>
 __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
                                           uint32_t &acc, WalkLane (&wl)[K], const ScanParams &p) {
@@ -94,10 +104,12 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
         walk16_count(q[0], t[0], acc, m);
         return;
     }
-    uint32_t q0[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) q0[s] = q[s];
-    const uint32_t acc0 = acc;
+    if constexpr (MODE == kCountPerWalk && !GUARD && K == 1) {
+        uint32_t hm;
+        walk16_hits(q[0], t[0], hm, m);
+        if (__ballot(hm != 0)) record_hits(hm, jb, wl[0]);
+        return;
+    }
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
 #pragma unroll
@@ -105,38 +117,20 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
 #pragma unroll
             for (int s = 0; s < K; ++s) {
                 const uint32_t c = (t[s][w] >> (8 * b)) & 0xffu;
+                const uint32_t j = jb + uint32_t(4 * w + b);
                 q[s] = table_step(q[s], c);
                 bool hit = q[s] == m;
-                if (GUARD) hit = hit && (jb + uint32_t(4 * w + b) < wl[s].len);
-                if (MODE != kPositions) {
+                if (GUARD) hit = hit && (j < wl[s].len);
+                if (MODE == kCount) {
                     add_hits(acc, hit);
-                } else if (hit) {
-                    if (wl[s].off < p.cap) p.positions[wl[s].off] = wl[s].wstart + jb + (4 * w + b) - (m - 1);
-                    ++wl[s].off;
-                }
-            }
-        }
-    }
-    if (MODE == kCountPerWalk && acc != acc0) {
-#pragma unroll
-        for (int s = 0; s < K; ++s) q[s] = q0[s];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-#pragma unroll
-                for (int s = 0; s < K; ++s) {
-                    const uint32_t c = (t[s][w] >> (8 * b)) & 0xffu;
-                    q[s] = table_step(q[s], c);
-                    const uint32_t j = jb + uint32_t(4 * w + b);
-                    bool hit = q[s] == m;
-                    if (GUARD) hit = hit && (j < wl[s].len);
+                } else if (MODE == kCountPerWalk) {
                     if (hit) {
-#pragma unroll
-                        for (int i = 0; i < kBuffered; ++i)
-                            if (wl[s].cnt == uint32_t(i)) wl[s].buf[i] = j;
+                        if (wl[s].cnt < uint32_t(kBuffered)) wl[s].buf[wl[s].cnt] = j;
                         ++wl[s].cnt;
                     }
+                } else if (hit) {
+                    if (wl[s].off < p.cap) p.positions[wl[s].off] = wl[s].wstart + j - (m - 1);
+                    ++wl[s].off;
                 }
             }
         }
@@ -218,8 +212,7 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
         wl[s].len = uint32_t(len);
         wl[s].cnt = 0;
         wl[s].off = 0;
-#pragma unroll
-        for (int i = 0; i < kBuffered; ++i) wl[s].buf[i] = 0;
+        wl[s].buf = MODE == kCountPerWalk ? p.walk_buf + g * kBuffered : nullptr;
         q[s] = 0;
         if (MODE == kPositions) {
             // only walks whose matches did not all fit the counting pass's buffer
@@ -328,17 +321,17 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     if (MODE == kPositions) return;
 
     if (MODE == kCountPerWalk) {
+        uint32_t c = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int64_t g = g0 + s * kWave + lane;
-            if (g < p.nwalks) {
-                p.walk_count[g] = wl[s].cnt;
-                if (wl[s].cnt != 0) {
-#pragma unroll
-                    for (int i = 0; i < kBuffered; ++i) p.walk_buf[g * kBuffered + i] = wl[s].buf[i];
-                }
-            }
+            if (g < p.nwalks) p.walk_count[g] = wl[s].cnt;
+            c += wl[s].cnt;
         }
+        // the wave's matches, summed over its lanes
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) c += uint32_t(__shfl_xor(int(c), o));
+        acc = uint32_t(__builtin_amdgcn_readfirstlane(int(c)));
     }
     // workgroup sum in LDS (reusing the first transpose buffer), one atomic
     unsigned long long *red = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(p.m));
@@ -352,88 +345,148 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     }
 }
 
-// Positions of walks with 1..kBuffered matches, from the counting pass's
-// buffer: start = walk start + end offset - (m - 1).
-__global__ __launch_bounds__(256) void k_scatter_buffered(const uint32_t *walk_count, const uint32_t *walk_buf,
-                                                          const int64_t *walk_off, int64_t nwalks, int64_t S,
-                                                          int32_t m, int64_t *positions, int64_t cap) {
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < nwalks;
-         g += int64_t(gridDim.x) * blockDim.x) {
-        const uint32_t c = walk_count[g];
-        if (c == 0 || c > uint32_t(kBuffered)) continue;
-        const int64_t o = walk_off[g];
-        for (uint32_t i = 0; i < c; ++i)
-            if (o + i < cap) positions[o + i] = g * S + int64_t(walk_buf[g * kBuffered + i]) - (m - 1);
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Small helper kernels: zero the count, prefix-sum the per-walk counts.
+// Per-walk offsets and the buffered positions.  Blocks of 256 threads; every
+// global access is a coalesced pass over consecutive walks, staged in LDS.
 // ---------------------------------------------------------------------------
 
 __global__ void k_zero_u64(unsigned long long *x) { *x = 0; }
 
 constexpr int kScanThreads = 256;
-constexpr int kScanPerThread = 16;
-constexpr int kScanBlock = kScanThreads * kScanPerThread;
+constexpr int kScanPerThread = 4;
+constexpr int kScanBlock = kScanThreads * kScanPerThread;  // walks per block of the offset passes
 
-// exclusive scan over the block's threads (in place on `v`), returns the block total
-__device__ unsigned long long block_exclusive_scan(unsigned long long &v) {
-    __shared__ unsigned long long sh[kScanThreads];
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        unsigned long long add = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+__device__ __forceinline__ unsigned long long wave_inclusive_scan(unsigned long long v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long u = __shfl_up(v, d);
+        if (lane >= d) v += u;
     }
-    const unsigned long long incl = sh[threadIdx.x];
-    const unsigned long long total = sh[kScanThreads - 1];
-    __syncthreads();
-    v = incl - v;
-    return total;
+    return v;
 }
 
+// Exclusive scan of one value per thread over a 256-thread block; `sh` holds
+// 4 scratch slots in LDS; *total receives the block total.
+__device__ __forceinline__ unsigned long long block_exclusive_scan(unsigned long long v, unsigned long long *sh,
+                                                                   unsigned long long *total) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const unsigned long long inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) sh[w] = inc;
+    __syncthreads();
+    unsigned long long before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+        if (i < w) before += sh[i];
+        all += sh[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+// part[b] = matches of the walks of block b
 __global__ __launch_bounds__(kScanThreads) void k_walk_sums(const uint32_t *cnt, int64_t nw,
                                                             unsigned long long *part) {
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock + threadIdx.x * kScanPerThread;
+    __shared__ unsigned long long sh[kScanThreads / kWave];
+    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
     unsigned long long v = 0;
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (base + i < nw) v += cnt[base + i];
-    unsigned long long total = block_exclusive_scan(v);
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const int64_t g = base + i * kScanThreads + threadIdx.x;
+        if (g < nw) v += cnt[g];
+    }
+    unsigned long long total;
+    block_exclusive_scan(v, sh, &total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
 // one block: exclusive scan of the nb block totals; total match count to *count
 __global__ __launch_bounds__(kScanThreads) void k_scan_parts(unsigned long long *part, int64_t nb,
                                                              int64_t *count) {
+    __shared__ unsigned long long sh[kScanThreads / kWave];
     unsigned long long carry = 0;
     for (int64_t base = 0; base < nb; base += kScanThreads) {
         const int64_t i = base + threadIdx.x;
-        unsigned long long v = i < nb ? part[i] : 0;
-        unsigned long long tot = block_exclusive_scan(v);
-        if (i < nb) part[i] = v + carry;
+        const unsigned long long v = i < nb ? part[i] : 0;
+        unsigned long long tot;
+        const unsigned long long ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) part[i] = ex + carry;
         carry += tot;
-        __syncthreads();
     }
     if (threadIdx.x == 0) *count = int64_t(carry);
 }
 
+// off[g] = output offset of walk g: the block's counts are staged in LDS,
+// each thread scans 4 consecutive walks, and the offsets leave through LDS.
 __global__ __launch_bounds__(kScanThreads) void k_walk_offsets(const uint32_t *cnt, int64_t nw,
-                                                               const unsigned long long *part,
-                                                               int64_t *off) {
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock + threadIdx.x * kScanPerThread;
+                                                               const unsigned long long *part, int64_t *off) {
+    __shared__ unsigned long long sh[kScanThreads / kWave];
+    __shared__ uint32_t c_sh[kScanBlock];
+    __shared__ int64_t o_sh[kScanBlock];
+    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const int k = i * kScanThreads + threadIdx.x;
+        c_sh[k] = base + k < nw ? cnt[base + k] : 0u;
+    }
+    __syncthreads();
     unsigned long long v = 0;
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (base + i < nw) v += cnt[base + i];
-    block_exclusive_scan(v);
-    unsigned long long run = part[blockIdx.x] + v;
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (base + i < nw) {
-            off[base + i] = int64_t(run);
-            run += cnt[base + i];
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) v += c_sh[threadIdx.x * kScanPerThread + i];
+    unsigned long long total;
+    unsigned long long run = part[blockIdx.x] + block_exclusive_scan(v, sh, &total);
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const int k = threadIdx.x * kScanPerThread + i;
+        o_sh[k] = int64_t(run);
+        run += c_sh[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        const int k = i * kScanThreads + threadIdx.x;
+        if (base + k < nw) off[base + k] = o_sh[k];
+    }
+}
+
+// Positions of the walks with 1..kBuffered matches, from the counting pass's
+// buffer: start = walk start + end offset - (m - 1).  One block per 256 walks
+// enumerates the block's buffered matches in order (a scan of the buffered
+// counts in LDS) so that consecutive threads write consecutive positions;
+// the slots of walks with more matches are left to the positions pass.
+__global__ __launch_bounds__(kScanThreads) void k_scatter_buffered(const uint32_t *walk_count, const uint32_t *walk_buf,
+                                                                   const int64_t *walk_off, int64_t nwalks, int64_t S,
+                                                                   int32_t m, int64_t *positions, int64_t cap) {
+    __shared__ unsigned long long sh[kScanThreads / kWave];
+    __shared__ uint32_t first[kScanThreads + 1];  // buffered matches before each walk of the block
+    __shared__ int64_t out[kScanThreads];         // output offset of each walk
+    const int64_t g0 = int64_t(blockIdx.x) * kScanThreads;
+    const int64_t g = g0 + threadIdx.x;
+    uint32_t c = 0;
+    int64_t o = 0;
+    if (g < nwalks) {
+        c = walk_count[g];
+        o = walk_off[g];
+    }
+    const uint32_t b = c <= uint32_t(kBuffered) ? c : 0u;
+    unsigned long long total;
+    first[threadIdx.x] = uint32_t(block_exclusive_scan(b, sh, &total));
+    out[threadIdx.x] = o;
+    if (threadIdx.x == 0) first[kScanThreads] = uint32_t(total);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < uint32_t(total); k += kScanThreads) {
+        // the walk holding buffered match k: the last w with first[w] <= k
+        int lo = 0, hi = kScanThreads - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (first[mid] <= k) lo = mid; else hi = mid - 1;
         }
+        const uint32_t i = k - first[lo];
+        const int64_t dst = out[lo] + i;
+        const int64_t gw = g0 + lo;
+        if (dst < cap) positions[dst] = gw * S + int64_t(walk_buf[gw * kBuffered + i]) - (m - 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -725,12 +778,9 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, st, part, nb, count);
     hipLaunchKernelGGL(k_walk_offsets, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw,
                        (const unsigned long long *)part, woff);
-    {
-        const int64_t want = dfa::ceil_div(nw, 256);
-        const unsigned grid = unsigned(want < 65536 ? want : 65536);
-        hipLaunchKernelGGL(k_scatter_buffered, dim3(grid), dim3(256), 0, st, (const uint32_t *)wcnt,
-                           (const uint32_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions, cap);
-    }
+    hipLaunchKernelGGL(k_scatter_buffered, dim3(unsigned(dfa::ceil_div(nw, kScanThreads))), dim3(kScanThreads), 0, st,
+                       (const uint32_t *)wcnt, (const uint32_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions,
+                       cap);
     if (!hip_ok(hipGetLastError(), "prefix-sum launch")) return DFA_EHIP;
     sp.walk_off = woff;
     sp.positions = positions;

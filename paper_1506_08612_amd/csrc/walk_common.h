@@ -192,6 +192,115 @@ __device__ __forceinline__ void walk16_count(uint32_t &q, const v4u &t, uint32_t
     acc = s;
 }
 
+// The same sixteen steps, recording which of them reached the final state:
+// `hm` gets one bit per byte, the first byte in bit 15 and the last in bit 0
+// (each step doubles hm and adds the step's compare result as a carry), so a
+// lane's matches in the unit end at bytes 15 - (set bit positions).
+__device__ __forceinline__ void walk16_hits(uint32_t &q, const v4u &t, uint32_t &hm, uint32_t m) {
+    uint32_t qb, a, c;
+    unsigned long long mk, co;
+    asm(
+        "v_mov_b32 %[hm], 0\n\t"
+        "v_bfe_u32 %[c], %[w0], 0, 8\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 8, 8\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 0, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 8, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 16, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 24, 8\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[qb]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_cmp_eq_u32_e64 %[mk], %[m], %[q]\n\t"
+        "v_addc_co_u32_e64 %[hm], %[co], %[hm], %[hm], %[mk]\n\t"
+        : [q] "+v"(q), [qb] "=&v"(qb), [a] "=&v"(a), [c] "=&v"(c), [hm] "=&v"(hm), [mk] "=&s"(mk), [co] "=&s"(co)
+        : [w0] "v"(t.x), [w1] "v"(t.y), [w2] "v"(t.z), [w3] "v"(t.w), [m] "s"(m), [row] "s"(uint32_t(kRow)));
+}
+
 // 16 bytes at text[a..a+15]; bytes at or past n read as 0 (a byte outside
 // every pattern: it sends the automaton to q0 and never completes a match).
 __device__ __forceinline__ v4u load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
