@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     transition_table,
     automaton_scan,
     pair_counts,
+    degenerate_count,
     lib_path,
     OracleLib,
 )

@@ -34,6 +34,13 @@
  *   oracle_pair_counts      -- the occurrence count of Sec. II.A applied to
  *                              every (text segment, pattern) pair of a batch.
  *
+ *   oracle_degenerate_count -- start positions where a degenerate pattern
+ *                              (IUPAC nucleotide codes) or, on request, its
+ *                              reverse complement matches: the structure of
+ *                              the paper's pattern table (Table 3), where
+ *                              each 8-mer is paired with its reverse
+ *                              complement and carries a 3-way alternative.
+ *
  * Parity pins (tests/test_oracle_pins.py): Python's regex engine with a
  * lookahead (an independent library routine for overlapping matches),
  * closed forms on periodic texts, additivity over concatenation, reverse
@@ -140,4 +147,81 @@ int oracle_pair_counts(const uint8_t *text, const int64_t *seg_off,
         if (counts[p] < 0) return -1;
     }
     return 0;
+}
+
+/* The bases an IUPAC code stands for, as a bit set (A=1, C=2, G=4, T=8); 0 for
+ * a byte that is not a code.  A text byte matches a code iff it is one of the
+ * bases A, C, G, T in the code's set: a text 'N' (an unknown base) matches
+ * nothing. */
+static int iupac_bases(uint8_t c)
+{
+    switch (c) {
+    case 'A': return 1;
+    case 'C': return 2;
+    case 'G': return 4;
+    case 'T': return 8;
+    case 'R': return 1 | 4;          /* purine */
+    case 'Y': return 2 | 8;          /* pyrimidine */
+    case 'S': return 2 | 4;
+    case 'W': return 1 | 8;
+    case 'K': return 4 | 8;
+    case 'M': return 1 | 2;
+    case 'B': return 2 | 4 | 8;      /* not A */
+    case 'D': return 1 | 4 | 8;      /* not C */
+    case 'H': return 1 | 2 | 8;      /* not G */
+    case 'V': return 1 | 2 | 4;      /* not T */
+    case 'N': return 1 | 2 | 4 | 8;
+    default: return 0;
+    }
+}
+
+static int base_bit(uint8_t x)
+{
+    switch (x) {
+    case 'A': return 1;
+    case 'C': return 2;
+    case 'G': return 4;
+    case 'T': return 8;
+    default: return 0;
+    }
+}
+
+/* The complement of a code: the code of the complementary bases (A<->T, C<->G). */
+static uint8_t iupac_complement(uint8_t c)
+{
+    int b = iupac_bases(c), r = 0;
+    if (b & 1) r |= 8;
+    if (b & 8) r |= 1;
+    if (b & 2) r |= 4;
+    if (b & 4) r |= 2;
+    static const char code_of[16] = {0, 'A', 'C', 'M', 'G', 'R', 'S', 'V',
+                                     'T', 'W', 'Y', 'H', 'K', 'D', 'B', 'N'};
+    return (uint8_t)code_of[r];
+}
+
+/* Does the degenerate pattern p[0..m-1] match text[i..i+m-1]? */
+static int degenerate_at(const uint8_t *text, int64_t i, const uint8_t *p, int64_t m)
+{
+    for (int64_t j = 0; j < m; ++j)
+        if (!(iupac_bases(p[j]) & base_bit(text[i + j]))) return 0;
+    return 1;
+}
+
+/* Number of start positions i (0 <= i <= n-m) where the degenerate pattern
+ * matches, or (both_strands != 0) where it or its reverse complement matches
+ * -- one count per position.  Returns -1 for m < 1, m > 255 or a byte of pat
+ * that is not an IUPAC code. */
+int64_t oracle_degenerate_count(const uint8_t *text, int64_t n, const uint8_t *pat,
+                                int64_t m, int both_strands)
+{
+    uint8_t rc[255];
+    if (m < 1 || m > 255 || n < 0) return -1;
+    for (int64_t j = 0; j < m; ++j) {
+        if (!iupac_bases(pat[j])) return -1;
+        rc[m - 1 - j] = iupac_complement(pat[j]);
+    }
+    int64_t count = 0;
+    for (int64_t i = 0; i + m <= n; ++i)
+        if (degenerate_at(text, i, pat, m) || (both_strands && degenerate_at(text, i, rc, m))) ++count;
+    return count;
 }

@@ -54,6 +54,8 @@ class OracleLib:
         lib.oracle_pair_counts.restype = ctypes.c_int
         lib.oracle_pair_counts.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, _i64p,
                                            ctypes.c_int64, _i64p, _i64p, ctypes.c_int64, _i64p]
+        lib.oracle_degenerate_count.restype = ctypes.c_int64
+        lib.oracle_degenerate_count.argtypes = [_u8p, ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_int]
         self.lib = lib
 
     # -- definitions (see oracle.c) ------------------------------------------------------
@@ -118,6 +120,17 @@ class OracleLib:
         return out
 
 
+    def degenerate_count(self, text, pattern, both_strands: bool = False) -> int:
+        """Start positions where the IUPAC pattern (or, with both_strands, its reverse
+        complement) matches; one count per position."""
+        t = _as_u8(text)
+        p = _as_u8(pattern)
+        r = self.lib.oracle_degenerate_count(_p(t, _u8p), t.size, _p(p, _u8p), p.size, 1 if both_strands else 0)
+        if r < 0:
+            raise ValueError("bad degenerate pattern")
+        return int(r)
+
+
 def _load() -> OracleLib:
     global _lib
     with _lock:
@@ -158,3 +171,7 @@ def automaton_scan(table, text) -> np.ndarray:
 
 def pair_counts(text, seg_off, patterns, pair_seg, pair_pat) -> np.ndarray:
     return _load().pair_counts(text, seg_off, patterns, pair_seg, pair_pat)
+
+
+def degenerate_count(text, pattern, both_strands: bool = False) -> int:
+    return _load().degenerate_count(text, pattern, both_strands)
