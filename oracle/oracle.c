@@ -221,7 +221,7 @@ int64_t oracle_degenerate_count(const uint8_t *text, int64_t n, const uint8_t *p
         rc[m - 1 - j] = iupac_complement(pat[j]);
     }
     int64_t count = 0;
-    for (int64_t i = 0; i + m <= n; ++i)
+    for (int64_t i = 0; i <= n - m; ++i)
         if (degenerate_at(text, i, pat, m) || (both_strands && degenerate_at(text, i, rc, m))) ++count;
     return count;
 }
