@@ -202,7 +202,8 @@ typedef struct dfa_merged_plan {
     int64_t nautomata;       /* merged automata built */
     int64_t nstates;         /* states over all automata */
     int64_t nfinal;          /* reporting states over all automata */
-    int64_t npairs;          /* counters written by dfa_merged_run */
+    int64_t npairs;          /* (segment, pattern) pairs */
+    int64_t ncounts;         /* counters written by dfa_merged_run */
     int64_t text_bytes;      /* bytes the segments span (seg_off[nseg]) */
     int64_t workspace_bytes; /* device bytes the plan occupies (automata, items, visit counters) */
     int64_t items_offset;    /* layout of the plan inside the workspace */
@@ -216,7 +217,10 @@ typedef struct dfa_merged_plan {
 
 /* Batched counting with merged automata: same question as the dfa_batch_*
  * calls (pair k asks for the occurrences of pattern pair_pat[k] inside
- * segment pair_seg[k]), but the patterns are passed as bytes
+ * segment pair_seg[k]; pair_dst, if not NULL, sends pair k's count to
+ * counter pair_dst[k] < ncounts, where the counts of all pairs sent to one
+ * counter add up -- with NULL, counter k is pair k and ncounts must be 0 or
+ * npairs), but the patterns are passed as bytes
  * (patterns[pat_off[j] ..], pat_len[j] in 1..DFA_MAX_M, host) and the pairs
  * of each segment are merged into as few automata as the LDS budget
  * (tune->automaton_bytes) allows, so that one table lookup per text byte
@@ -233,7 +237,7 @@ typedef struct dfa_merged_plan {
  *                       256-byte aligned); with workspace == NULL only fills
  *                       `plan`.  Synchronises `stream`.
  *   dfa_merged_run      device only: clears the counters it owns, zeroes
- *                       counts[0..npairs-1] (int64, device, 8-byte aligned) and
+ *                       counts[0..ncounts-1] (int64, device, 8-byte aligned) and
  *                       launches the scan and the count reduction; `text`
  *                       (device, n >= plan->text_bytes, 16-byte aligned).
  *                       Asynchronous, allocates nothing, no memset nodes; the
@@ -243,11 +247,31 @@ typedef struct dfa_merged_plan {
 int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns,
                        const int64_t *pat_off, const int32_t *pat_len, int32_t npat,
                        const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
+                       const int32_t *pair_dst, int64_t ncounts,
                        void *workspace, int64_t workspace_bytes, const dfa_tune *tune,
                        dfa_merged_plan *plan, void *stream);
 
 int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, const dfa_merged_plan *plan,
                    int64_t *counts, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Degenerate patterns (the structure of Table 3: IUPAC codes, both strands) */
+/* ------------------------------------------------------------------------ */
+
+#define DFA_DEGENERATE_MAX_KMERS (1 << 20)
+
+/* Host-only.  Expands code[0..m-1] (IUPAC nucleotide codes A C G T R Y S W K
+ * M B D H V N, upper case; 1 <= m <= DFA_MAX_M) into the distinct plain
+ * k-mers over A, C, G, T it matches -- and, if both_strands, those its
+ * reverse complement matches -- sorted, m bytes each, back to back in `out`
+ * (host, room for out_cap k-mers; NULL for a size query).  A text position
+ * matches the degenerate pattern (on either strand) iff exactly one of these
+ * k-mers starts there, so its count is the sum of theirs; a text byte that is
+ * not A, C, G or T (e.g. 'N') matches no code.  Returns the number of k-mers,
+ * DFA_EINVAL (bad code or length, more than DFA_DEGENERATE_MAX_KMERS) or
+ * DFA_ENOSPACE. */
+int64_t dfa_degenerate_expand(const uint8_t *code, int32_t m, int32_t both_strands, uint8_t *out,
+                              int64_t out_cap);
 
 #ifdef __cplusplus
 }

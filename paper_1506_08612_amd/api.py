@@ -66,6 +66,7 @@ class MergedPlan(ctypes.Structure):
         ("nstates", ctypes.c_int64),
         ("nfinal", ctypes.c_int64),
         ("npairs", ctypes.c_int64),
+        ("ncounts", ctypes.c_int64),
         ("text_bytes", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_int64),
         ("items_offset", ctypes.c_int64),
@@ -99,8 +100,9 @@ SIGNATURES = {
     "dfa_count_batch": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _i64,
                                        _vp, _vp, _i64, _TuneP, _vp]),
     "dfa_ac_build": (_i64, [_vp, _vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp]),
-    "dfa_merged_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
-                                          _MPlanP, _vp]),
+    "dfa_merged_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
+                                          _TuneP, _MPlanP, _vp]),
+    "dfa_degenerate_expand": (_i64, [_vp, _i32, _i32, _vp, _i64]),
     "dfa_merged_run": (ctypes.c_int, [_vp, _i64, _vp, _MPlanP, _vp, _vp]),
 }
 
@@ -347,25 +349,31 @@ def ac_build(patterns) -> AcTable:
 
 class MergedBatch:
     """Batched counting with merged automata: (segments, patterns, pairs) planned and
-    uploaded once; run() is device-only and may be captured in a HIP graph."""
+    uploaded once; run() is device-only and may be captured in a HIP graph.  With
+    `pair_dst`, pair k's count goes to counter pair_dst[k] (counts of pairs sharing a
+    counter add up) and there are `ncounts` counters."""
 
     def __init__(self, seg_off, patterns, pair_seg, pair_pat, t: Optional[Tune] = None, device="cuda",
-                 stream=None):
+                 stream=None, pair_dst=None, ncounts: int = 0):
         torch = _torch()
         self.seg_off = _np(seg_off, np.int64)
         self.pair_seg = _np(pair_seg, np.int32)
         self.pair_pat = _np(pair_pat, np.int32)
+        self.pair_dst = None if pair_dst is None else _np(pair_dst, np.int32)
+        self.ncounts = int(ncounts) if pair_dst is not None else self.pair_seg.size
         self.patterns, self._blob, self._offs, self._lens = _pack_patterns(patterns)
         self.plan = MergedPlan()
         self._prep(None, 0, t, stream)
         self.workspace = torch.empty(max(256, self.plan.workspace_bytes), dtype=torch.uint8, device=device)
         self._prep(self.workspace.data_ptr(), self.workspace.numel(), t, stream)
-        self.counts = torch.zeros(max(1, self.pair_seg.size), dtype=torch.int64, device=device)
+        self.counts = torch.zeros(max(1, self.ncounts), dtype=torch.int64, device=device)
 
     def _prep(self, ws, wsb, t, stream):
+        dst = self.pair_dst.ctypes.data if self.pair_dst is not None else None
         _check(lib.dfa_merged_prepare(self.seg_off.ctypes.data, self.seg_off.size - 1, self._blob.ctypes.data,
                                       self._offs.ctypes.data, self._lens.ctypes.data, len(self.patterns),
                                       self.pair_seg.ctypes.data, self.pair_pat.ctypes.data, self.pair_seg.size,
+                                      dst, self.ncounts if dst is not None else 0,
                                       ws, wsb, _tune_ptr(t), ctypes.byref(self.plan), _stream_handle(stream)))
 
     def run(self, text, stream=None):
@@ -373,13 +381,60 @@ class MergedBatch:
         _check(lib.dfa_merged_run(text.data_ptr() if text.numel() else None, text.numel(),
                                   self.workspace.data_ptr(), ctypes.byref(self.plan), self.counts.data_ptr(),
                                   _stream_handle(stream)))
-        return self.counts[:self.pair_seg.size]
+        return self.counts[:self.ncounts]
 
 
 def count_merged(text, seg_off, patterns, pair_seg, pair_pat, t: Optional[Tune] = None,
                  stream=None) -> np.ndarray:
     """Per-pair occurrence counts with merged automata (synchronises)."""
     b = MergedBatch(seg_off, patterns, pair_seg, pair_pat, t, device=text.device, stream=stream)
+    return b.run(text, stream).cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# degenerate patterns
+# ---------------------------------------------------------------------------
+
+def expand_degenerate(code: bytes, both_strands: bool = False):
+    """The distinct plain k-mers an IUPAC pattern (and, with both_strands, its reverse
+    complement) matches, sorted."""
+    c = np.frombuffer(bytes(code), dtype=np.uint8).copy()
+    k = _check(lib.dfa_degenerate_expand(c.ctypes.data, c.size, int(both_strands), None, 0))
+    out = np.empty(max(1, k * c.size), dtype=np.uint8)
+    _check(lib.dfa_degenerate_expand(c.ctypes.data, c.size, int(both_strands), out.ctypes.data, k))
+    m = c.size
+    return [out[i * m:(i + 1) * m].tobytes() for i in range(k)]
+
+
+class DegenerateBatch:
+    """Counts of degenerate patterns: query q asks for the start positions in segment
+    seg[q] where code[q] (IUPAC) -- or, if both[q], its reverse complement -- matches.
+    Every query becomes its expansions, each a pair of one merged scan whose count goes
+    to the query's counter."""
+
+    def __init__(self, seg_off, queries, t: Optional[Tune] = None, device="cuda", stream=None):
+        pats, pseg, ppat, pdst = [], [], [], []
+        index = {}
+        for q, (seg, code, both) in enumerate(queries):
+            for km in expand_degenerate(code, both):
+                j = index.setdefault(km, len(pats))
+                if j == len(pats):
+                    pats.append(km)
+                pseg.append(int(seg))
+                ppat.append(j)
+                pdst.append(q)
+        self.nqueries = len(queries)
+        self.batch = MergedBatch(seg_off, pats or [b"A"], pseg, ppat, t, device=device, stream=stream,
+                                 pair_dst=pdst, ncounts=self.nqueries)
+        self.counts = self.batch.counts
+
+    def run(self, text, stream=None):
+        return self.batch.run(text, stream)
+
+
+def count_degenerate(text, seg_off, queries, t: Optional[Tune] = None, stream=None) -> np.ndarray:
+    """Per-query counts of degenerate patterns (synchronises)."""
+    b = DegenerateBatch(seg_off, queries, t, device=text.device, stream=stream)
     return b.run(text, stream).cpu().numpy()
 
 

@@ -34,6 +34,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def host_cxx() -> str:
+    for c in (os.environ.get("CXX"), shutil.which("g++"), "/opt/rocm/llvm/bin/clang++"):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("no host C++ compiler found")
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
@@ -48,7 +55,8 @@ def build(verbose: bool = False, isa_dir: str | None = None) -> str:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [cc, *HIP_FLAGS, "-c", src, "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [cc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
+            # host-only sources: the host compiler, no device code object
+            cmd = [host_cxx(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
                    "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -83,7 +83,7 @@ struct MItem {
 };
 
 struct OutEntry {
-    int32_t pair;
+    int32_t pair;  // the counter the pattern's matches go to
     int32_t m;
 };
 
@@ -321,6 +321,8 @@ struct MHostPlan {
     int lds = 0;
     int64_t text_bytes = 0;
     int64_t nstates = 0;
+    int64_t ncounts = 0;
+    const int32_t *pair_dst = nullptr;  // counter of each pair (null: the pair itself)
 };
 
 int64_t auto_lds_bytes(const MAuto &a) {
@@ -359,7 +361,8 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     for (int32_t f = 0; f < a.nstates - a.first_final; ++f) {
         for (int32_t e = a.out_off[size_t(f)]; e < a.out_off[size_t(f) + 1]; ++e) {
             const int64_t k = ks[size_t(a.out_pat[size_t(e)])];
-            hp.out_ent.push_back(OutEntry{int32_t(k), pat_len[pair_pat[k]]});
+            const int32_t dst = hp.pair_dst ? hp.pair_dst[k] : int32_t(k);
+            hp.out_ent.push_back(OutEntry{dst, pat_len[pair_pat[k]]});
         }
         if (hp.out_ent.size() > size_t(0x7fffffff)) {
             dfa::set_error("dfa_merged: too many output entries");
@@ -374,7 +377,26 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
 
 int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, const int64_t *pat_off,
                 const int32_t *pat_len, int32_t npat, const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
-                const dfa_tune *t, MHostPlan &hp) {
+                const int32_t *pair_dst, int64_t ncounts, const dfa_tune *t, MHostPlan &hp) {
+    if (!pair_dst) {
+        if (ncounts != 0 && ncounts != npairs) {
+            dfa::set_error("dfa_merged: without pair_dst, ncounts must be 0 or npairs");
+            return DFA_EINVAL;
+        }
+        ncounts = npairs;
+    }
+    if (ncounts < 0 || ncounts > 0x7fffffff) {
+        dfa::set_error("dfa_merged: ncounts=%lld out of range", (long long)ncounts);
+        return DFA_EINVAL;
+    }
+    for (int64_t k = 0; pair_dst && k < npairs; ++k)
+        if (pair_dst[k] < 0 || pair_dst[k] >= ncounts) {
+            dfa::set_error("dfa_merged: pair_dst[%lld]=%d outside [0, %lld)", (long long)k, pair_dst[k],
+                           (long long)ncounts);
+            return DFA_EINVAL;
+        }
+    hp.ncounts = ncounts;
+    hp.pair_dst = pair_dst;
     if (nseg < 0 || npat < 0 || npairs < 0 || (nseg > 0 && !seg_off) ||
         (npat > 0 && (!patterns || !pat_off || !pat_len)) || (npairs > 0 && (!pair_seg || !pair_pat))) {
         dfa::set_error("dfa_merged: bad counts or null arrays");
@@ -553,7 +575,8 @@ WsLayout ws_layout(const MHostPlan &hp) {
 
 extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns,
                                   const int64_t *pat_off, const int32_t *pat_len, int32_t npat,
-                                  const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs, void *workspace,
+                                  const int32_t *pair_seg, const int32_t *pair_pat, int64_t npairs,
+                                  const int32_t *pair_dst, int64_t ncounts, void *workspace,
                                   int64_t workspace_bytes, const dfa_tune *tune, dfa_merged_plan *plan,
                                   void *stream) {
     if (!plan) {
@@ -561,7 +584,8 @@ extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const ui
         return DFA_EINVAL;
     }
     MHostPlan hp;
-    int rc = plan_merged(seg_off, nseg, patterns, pat_off, pat_len, npat, pair_seg, pair_pat, npairs, tune, hp);
+    int rc = plan_merged(seg_off, nseg, patterns, pat_off, pat_len, npat, pair_seg, pair_pat, npairs, pair_dst,
+                         ncounts, tune, hp);
     if (rc != DFA_OK) return rc;
     // the automata's table offsets are relative to the area: make them workspace offsets
     const WsLayout L = ws_layout(hp);
@@ -572,6 +596,7 @@ extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const ui
     plan->nstates = hp.nstates;
     plan->nfinal = int64_t(hp.out_off.size()) - 1;
     plan->npairs = npairs;
+    plan->ncounts = hp.ncounts;
     plan->text_bytes = hp.text_bytes;
     plan->workspace_bytes = L.total;
     plan->items_offset = L.items;
@@ -615,7 +640,7 @@ extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const ui
 
 extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, const dfa_merged_plan *plan,
                               int64_t *counts, void *stream) {
-    if (!plan || n < 0 || (!text && n > 0) || (plan->npairs > 0 && !counts) || (plan->nitems > 0 && !workspace)) {
+    if (!plan || n < 0 || (!text && n > 0) || (plan->ncounts > 0 && !counts) || (plan->nitems > 0 && !workspace)) {
         dfa::set_error("dfa_merged_run: null argument or n < 0");
         return DFA_EINVAL;
     }
@@ -639,10 +664,10 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
     uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
     unsigned long long *visits = reinterpret_cast<unsigned long long *>(ws + plan->visits_offset);
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counts);
-    if (plan->npairs + plan->nfinal > 0) {
-        const int64_t want = dfa::ceil_div(plan->npairs + plan->nfinal, 256);
+    if (plan->ncounts + plan->nfinal > 0) {
+        const int64_t want = dfa::ceil_div(plan->ncounts + plan->nfinal, 256);
         hipLaunchKernelGGL(k_merged_zero, dim3(unsigned(std::min<int64_t>(want, 4096))), dim3(256), 0, st, cnt,
-                           plan->npairs, visits, plan->nfinal);
+                           plan->ncounts, visits, plan->nfinal);
         if (!hip_ok(hipGetLastError(), "k_merged_zero launch")) return DFA_EHIP;
     }
     if (plan->nitems == 0) {

@@ -179,7 +179,7 @@ class Server:
         def prepare(ws, wsb, stream):
             api._check(api.lib.dfa_merged_prepare(so.ctypes.data, so.size - 1, blob.ctypes.data, offs.ctypes.data,
                                                   lens.ctypes.data, len(pats), ps_a.ctypes.data, pp_a.ctypes.data,
-                                                  ps_a.size, ws, wsb, api._tune_ptr(self.tune),
+                                                  ps_a.size, None, 0, ws, wsb, api._tune_ptr(self.tune),
                                                   api.ctypes.byref(plan), stream))
 
         prepare(None, 0, None)

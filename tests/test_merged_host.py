@@ -90,7 +90,7 @@ def _prepare(seg_off, patterns, pair_seg, pair_pat, t=None):
     plan = api.MergedPlan()
     rc = api.lib.dfa_merged_prepare(so.ctypes.data, so.size - 1, blob.ctypes.data, offs.ctypes.data,
                                     lens.ctypes.data, len(pats), ps.ctypes.data, pp.ctypes.data, ps.size, None, 0,
-                                    api._tune_ptr(t), ctypes.byref(plan), None)
+                                    None, 0, api._tune_ptr(t), ctypes.byref(plan), None)
     return rc, plan
 
 
