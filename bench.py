@@ -127,8 +127,9 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
     sb = api.Batch([0, n], ps, pair_seg, pair_pat)
     sep_ms = _events_ms(torch, lambda: sb.run(d), 1)
     sep_equal = bool(np.array_equal(sb.counts.cpu().numpy()[:npat], ref))
+    deg = bench_degenerate(torch, api, d, n)
     pb = n * npat
-    return {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), per-pattern counts",
+    return deg, {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), per-pattern counts",
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1),
             "one_per_launch_pattern_bytes_per_s": round(pb / (base_ms * 1e-3), 1),
             "speedup_vs_one_per_launch": round(base_ms / ms, 2),
@@ -139,6 +140,30 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
             "separate_automata": {"ms": round(sep_ms, 3), "pattern_bytes_per_s": round(pb / (sep_ms * 1e-3), 1),
                                   "speedup_vs_one_per_launch": round(base_ms / sep_ms, 2),
                                   "counts_equal_one_per_launch": sep_equal}}
+
+
+def bench_degenerate(torch, api, d, n):
+    """18 degenerate queries shaped like the paper's pattern table: 9 random 8-mers with one
+    position taking one of three bases (IUPAC B/D/H/V), each counted on both strands, and 9
+    plain random 8-mers on both strands."""
+    from paper_1506_08612_amd import graph, synth
+    rng = np.random.default_rng([6, 0x4447])
+    codes = []
+    for i in range(9):
+        s = list(synth.random_pattern(8, rng).decode())
+        s[i % 8] = "BDHV"[int(rng.integers(0, 4))]
+        codes.append("".join(s).encode())
+    codes += [synth.random_pattern(8, rng) for _ in range(9)]
+    queries = [(0, c, True) for c in codes]
+    b = api.DegenerateBatch([0, n], queries, device=d.device)
+    g = graph.GraphedBatch(d, b)
+    ms = _events_ms(torch, g.replay, 5)
+    nk = int(b.batch.plan.npairs)
+    return {"workload": f"{len(queries)} degenerate 8-mer queries (9 with a 3-way position), both strands, "
+                        f"over the same {n} B text; {nk} plain k-mers after expansion",
+            "ms": round(ms, 3), "text_GBps": round(n / ms / 1e6, 1),
+            "query_bytes_per_s": round(n * len(queries) / (ms * 1e-3), 1),
+            "counts": [int(x) for x in b.counts.cpu().numpy()[:len(queries)]]}
 
 
 def bench_segmented(torch, api, synth):
@@ -220,7 +245,7 @@ def main(argv=None) -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if a.only:
-        legs = {"batched": lambda: bench_batched(torch, api, synth),
+        legs = {"batched": lambda: bench_batched(torch, api, synth)[1],
                 "segmented": lambda: bench_segmented(torch, api, synth),
                 "serving": lambda: bench_serving(torch, a.serve_queries)}
         print(json.dumps({a.only: legs[a.only]()}), flush=True)
@@ -356,7 +381,7 @@ def main(argv=None) -> int:
     if not a.skip_extra:
         del dtext
         torch.cuda.empty_cache()
-        extra["batched"] = bench_batched(torch, api, synth)
+        extra["degenerate"], extra["batched"] = bench_batched(torch, api, synth)
         torch.cuda.empty_cache()
         extra["segmented"] = bench_segmented(torch, api, synth)
         torch.cuda.empty_cache()

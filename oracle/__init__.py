@@ -18,4 +18,4 @@ from .oracle import (  # noqa: F401
     lib_path,
     OracleLib,
 )
-from . import ac  # noqa: F401,E402
+from . import ac, fasta  # noqa: F401,E402
