@@ -273,6 +273,31 @@ int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, const dfa_me
 int64_t dfa_degenerate_expand(const uint8_t *code, int32_t m, int32_t both_strands, uint8_t *out,
                               int64_t out_cap);
 
+/* ------------------------------------------------------------------------ */
+/* FASTA input (the paper's genomes, Table 1, are FASTA text)                */
+/* ------------------------------------------------------------------------ */
+
+/* Device workspace for dfa_fasta_normalize on n bytes (0 for n == 0). */
+int64_t dfa_fasta_workspace_bytes(int64_t n);
+
+/* Device-only.  Turns FASTA text raw[0..n-1] (device, 4-byte aligned) into
+ * plain sequence: a line whose first byte is '>' is a header (it starts a
+ * record; none of its bytes are kept); every other byte is kept except '
+'
+ * and '', with 'a'..'z' made upper case (soft-masking dropped).
+ *   out        device, room for n bytes: the kept bytes, in order
+ *   rec_start  device int64, room for rec_cap entries: where each record's
+ *              sequence starts in `out` (the first rec_cap records)
+ *   totals     device int64[2]: {kept bytes, records} (exact even past rec_cap)
+ *   workspace  device, dfa_fasta_workspace_bytes(n) bytes, 256-byte aligned
+ * Kept bytes before the first header (normally none) precede record 0.  With
+ * seg_off = {rec_start..., totals[0]} the records are the segments of the
+ * batched scans.  Asynchronous; returns DFA_OK, DFA_EINVAL, DFA_ENOSPACE or
+ * DFA_EHIP. */
+int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, int64_t *rec_start,
+                        int64_t rec_cap, int64_t *totals, void *workspace, int64_t workspace_bytes,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,8 @@ SIGNATURES = {
     "dfa_merged_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                                           _TuneP, _MPlanP, _vp]),
     "dfa_degenerate_expand": (_i64, [_vp, _i32, _i32, _vp, _i64]),
+    "dfa_fasta_workspace_bytes": (_i64, [_i64]),
+    "dfa_fasta_normalize": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp]),
     "dfa_merged_run": (ctypes.c_int, [_vp, _i64, _vp, _MPlanP, _vp, _vp]),
 }
 
@@ -436,6 +438,28 @@ def count_degenerate(text, seg_off, queries, t: Optional[Tune] = None, stream=No
     """Per-query counts of degenerate patterns (synchronises)."""
     b = DegenerateBatch(seg_off, queries, t, device=text.device, stream=stream)
     return b.run(text, stream).cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# FASTA input
+# ---------------------------------------------------------------------------
+
+def fasta_normalize(raw, rec_cap: int = 1 << 16, stream=None):
+    """Normalise device FASTA text: returns (sequence, record starts) as device tensors
+    (uint8 view of the kept bytes, int64 starts of the first min(records, rec_cap)
+    records) and the exact (kept bytes, records) on the host (synchronises)."""
+    torch = _torch()
+    n = raw.numel()
+    dev = raw.device
+    out = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    rec = torch.empty(max(1, rec_cap), dtype=torch.int64, device=dev)
+    tot = torch.zeros(2, dtype=torch.int64, device=dev)
+    wsb = _check(lib.dfa_fasta_workspace_bytes(n))
+    ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=dev)
+    _check(lib.dfa_fasta_normalize(raw.data_ptr() if n else None, n, out.data_ptr(), rec.data_ptr(), rec_cap,
+                                   tot.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    kept, nrec = (int(x) for x in tot.cpu().tolist())
+    return out[:kept], rec[:min(nrec, rec_cap)], kept, nrec
 
 
 def exported_symbols() -> Sequence[str]:

@@ -1,0 +1,113 @@
+"""GPU parity of FASTA normalisation (dfa_fasta_normalize) against the oracle's
+definition (oracle/fasta.py): kept bytes and record starts bit-exact, including
+headers and line breaks that straddle the kernel's 64 KiB chunks; then counts on
+the normalised records."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fasta as ofasta
+from paper_1506_08612_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1506_08612_amd import api  # noqa: E402
+
+CHUNK = 64 * 1024
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def write_fasta(records, width, rng, crlf_frac=0.0, lower_frac=0.0):
+    out = bytearray()
+    for name, seq in records:
+        nl = b"\r\n" if rng.random() < crlf_frac else b"\n"
+        out += b">" + name + nl
+        s = bytearray(seq)
+        if lower_frac and len(s):
+            for _ in range(3):
+                a = int(rng.integers(0, len(s)))
+                b = min(len(s), a + int(rng.integers(1, 5000)))
+                s[a:b] = s[a:b].lower()
+        for i in range(0, len(s), width):
+            out += bytes(s[i:i + width]) + nl
+    return bytes(out)
+
+
+def check(raw: bytes, rec_cap=1 << 16):
+    d = api.to_device(np.frombuffer(raw, np.uint8).copy() if raw else np.zeros(0, np.uint8))
+    seq, rec, kept, nrec = api.fasta_normalize(d, rec_cap)
+    want_seq, want_starts = ofasta.normalize(raw)
+    assert kept == len(want_seq) and nrec == len(want_starts)
+    assert bytes(seq.cpu().numpy().tobytes()) == want_seq
+    assert rec.cpu().numpy().tolist() == want_starts[:rec_cap]
+    return seq, want_starts
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_genomes(seed):
+    rng = np.random.default_rng(seed)
+    recs = []
+    for k in range(int(rng.integers(1, 40))):
+        n = int(rng.choice([0, 1, 59, 60, 61, int(rng.integers(0, 200_000))]))
+        recs.append((f"rec{k} some description {seed}".encode(), synth.iid_gc41(n, 100 * seed + k).tobytes()))
+    for width in (60, 80, 7):
+        raw = write_fasta(recs, width, rng, crlf_frac=0.3, lower_frac=0.5)
+        say("seed", seed, "width", width, "bytes", len(raw))
+        check(raw)
+
+
+def test_chunk_boundary_cases():
+    # a header that starts exactly at a chunk start, one that straddles it, a newline as a
+    # chunk's last byte, a header longer than a chunk, no final newline, a preamble
+    body = b"ACGT" * (CHUNK // 4)
+    raw = bytearray(b"acgtn\n")                       # preamble before the first header
+    raw += body[:CHUNK - len(raw) - 1] + b"\n"          # this newline is the chunk's last byte
+    raw += b">at_chunk_start\n" + body[:1000] + b"\n"
+    pad = 2 * CHUNK - len(raw) - 3
+    raw += body[:pad] + b"\n>s"                        # header straddling the second boundary
+    raw += b"traddle header\n" + body[:5000] + b"\n"
+    raw += b">" + b"H" * (CHUNK + 123) + b"\n"          # header longer than a chunk
+    raw += body[:777] + b"\r\n>last\nAcGt"              # no final newline
+    check(bytes(raw))
+
+
+def test_edges():
+    check(b"")
+    check(b">only header")
+    check(b"\n\n\n")
+    check(b"AC>GT\nT")
+    check(b">a\n>b\n>c\nA\n")
+    rng = np.random.default_rng(7)
+    recs = [(b"r%d" % k, b"A" * 3) for k in range(5000)]
+    raw = write_fasta(recs, 60, rng)
+    seq, starts = check(raw, rec_cap=100)               # more records than rec_cap
+    assert len(starts) == 5000
+
+
+def test_counts_on_normalised_records():
+    rng = np.random.default_rng(11)
+    recs = [(b"chr%d" % k, synth.genome_like(int(rng.integers(1000, 400_000)), 200 + k, 0.02, 500).tobytes())
+            for k in range(12)]
+    raw = write_fasta(recs, 70, rng, lower_frac=1.0)
+    d = api.to_device(np.frombuffer(raw, np.uint8).copy())
+    seq, rec, kept, nrec = api.fasta_normalize(d)
+    seg_off = np.concatenate((rec.cpu().numpy(), [kept])).astype(np.int64)
+    pats = [synth.random_pattern(int(m), rng) for m in rng.integers(4, 20, size=10)]
+    pats += [recs[3][1][100:112]]
+    pair_seg = np.repeat(np.arange(nrec), len(pats))
+    pair_pat = np.tile(np.arange(len(pats)), nrec)
+    got = api.count_merged(seq, seg_off, pats, pair_seg, pair_pat)
+    text = b"".join(s for _, s in recs)
+    want = oracle.pair_counts(np.frombuffer(text, np.uint8), seg_off, pats, pair_seg, pair_pat)
+    assert np.array_equal(got, want)
