@@ -19,6 +19,8 @@ Also reported:
   automaton budget and shape, replayed from a HIP graph) against the same GPU
   running one count-only launch per pattern, in pattern-bytes/s; the batched
   scan with one automaton per pattern is timed beside it;
+* fasta -- the genome written as FASTA (24 records, 60 bases per line, 10 %
+  soft-masked) normalised on the device into plain sequence and record starts;
 * segmented -- 2000 contig-like segments (log-normal lengths, median 200 kB,
   ~2 GB, 2% 'N' runs), 1..16 patterns each, one merged launch;
 * serving -- 1000 Poisson arrivals (after 50 warm-up queries) of (text,
@@ -166,6 +168,95 @@ def bench_degenerate(torch, api, d, n):
             "counts": [int(x) for x in b.counts.cpu().numpy()[:len(queries)]]}
 
 
+def bench_study(torch, api, text, dtext, pats):
+    """Scalability and load balance of the count-only scan (analogues of the paper's
+    Figs. 5 and 7): throughput over genome sizes 0.2..3.2 GB (prefixes of the text), and
+    the spread of workgroup durations, the per-XCD busy time and the launch's tail at
+    3.2 GB for a sparse (m = 8) and a dense (m = 4) pattern."""
+    out = {"sizes": []}
+    res = torch.empty(1, dtype=torch.int64, device=dtext.device)
+    n = text.size
+    for gb in (0.2, 0.4, 0.8, 1.6, 3.2):
+        k = min(n, int(gb * 1e9)) // 16 * 16
+        row = {"bytes": k}
+        for p in pats:
+            if len(p) not in (4, 8):
+                continue
+            tab, m = api.device_table(p)
+            sub = dtext[:k]
+            ms = _events_ms(torch, lambda: api.count_async(sub, tab, m, res), 10)
+            row[f"m{m}_GBps"] = round(k / ms / 1e6, 1)
+        out["sizes"].append(row)
+    for p in pats:
+        if len(p) not in (4, 8):
+            continue
+        tab, m = api.device_table(p)
+        api.count_timed(dtext, tab, m)  # warm
+        c, t = api.count_timed(dtext, tab, m)
+        start, end, cyc = t[:, 0], t[:, 1], t[:, 2].astype(np.float64)
+        dur = (end - start).astype(np.float64)
+        span = float(end.max() - start.min())
+        q = np.percentile(cyc, [5, 50, 95, 99])
+        xcd = np.array([cyc[i::8].sum() for i in range(8)])
+        out[f"m{m}_workgroups"] = {
+            "count": int(c), "workgroups": int(t.shape[0]),
+            "cycles_p5_p50_p95_p99": [int(x) for x in q], "cycles_max_over_median": round(float(cyc.max() / q[1]), 3),
+            "xcd_busy_max_over_mean": round(float(xcd.max() / xcd.mean()), 4),
+            "tail_after_p95_end_frac": round(float((end.max() - np.percentile(end, 95)) / span), 4),
+            "mean_resident_workgroups": round(float(dur.sum() / span), 1),
+        }
+    return out
+
+
+def fasta_bytes(text: np.ndarray, nrec: int = 24, width: int = 60, seed: int = 8) -> np.ndarray:
+    """`text` written as FASTA: nrec records of near-equal length, `width` bases per line,
+    a header line per record, and 10 % of the bases soft-masked (lower case) in runs."""
+    rng = np.random.default_rng(seed)
+    n = text.size
+    cuts = np.linspace(0, n, nrec + 1).astype(np.int64)
+    parts = []
+    for k in range(nrec):
+        seq = text[cuts[k]:cuts[k + 1]].copy()
+        nmask = int(0.1 * seq.size / 5000)
+        for a in rng.integers(0, max(1, seq.size - 5000), size=nmask):
+            seg = seq[a:a + 5000]
+            np.add(seg, 32, out=seg, where=(seg >= 65) & (seg <= 90))  # upper -> lower case
+        parts.append(np.frombuffer(f">chr{k + 1} synthetic record {k + 1} of {nrec}\n".encode(), np.uint8))
+        full = seq.size // width
+        rows = np.empty((full, width + 1), np.uint8)
+        rows[:, :width] = seq[:full * width].reshape(full, width)
+        rows[:, width] = 10
+        parts.append(rows.reshape(-1))
+        if seq.size > full * width:
+            parts.append(np.concatenate((seq[full * width:], np.array([10], np.uint8))))
+    return np.concatenate(parts)
+
+
+def bench_fasta(torch, api, text, dtext, reps=5):
+    log("fasta: normalising the genome written as FASTA")
+    raw = fasta_bytes(text)
+    draw = api.to_device(raw)
+    n = raw.size
+    out = torch.empty(n, dtype=torch.uint8, device=draw.device)
+    rec = torch.empty(64, dtype=torch.int64, device=draw.device)
+    tot = torch.zeros(2, dtype=torch.int64, device=draw.device)
+    ws = torch.empty(max(256, api.lib.dfa_fasta_workspace_bytes(n)), dtype=torch.uint8, device=draw.device)
+
+    def run():
+        api._check(api.lib.dfa_fasta_normalize(draw.data_ptr(), n, out.data_ptr(), rec.data_ptr(), 64,
+                                               tot.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               api._stream_handle(None)))
+
+    ms = _events_ms(torch, run, reps)
+    kept, nrec = (int(x) for x in tot.cpu().tolist())
+    same = kept == text.size and bool(torch.equal(out[:kept], dtext))
+    del draw, out, ws
+    return {"workload": f"the {text.size} B genome as FASTA: {nrec} records, 60 bases per line, "
+                        f"10% soft-masked; {n} B of FASTA text",
+            "ms": round(ms, 3), "GBps": round(n / ms / 1e6, 1), "records": nrec,
+            "normalised_equals_source": same}
+
+
 def bench_segmented(torch, api, synth):
     from paper_1506_08612_amd import graph
     log("segmented: 2000 contig-like segments")
@@ -230,6 +321,8 @@ def main(argv=None) -> int:
     ap.add_argument("--skip-extra", action="store_true",
                     help="skip the batched, segmented and serving measurements")
     ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--study", action="store_true",
+                    help="also run the size sweep and workgroup load-balance study of the scan")
     ap.add_argument("--only", choices=("batched", "segmented", "serving"),
                     help="run only this leg and print its figures (for profiling)")
     a = ap.parse_args(argv)
@@ -378,7 +471,10 @@ def main(argv=None) -> int:
         parity_sample = ok
 
     extra = {}
+    if a.study:
+        extra["study"] = bench_study(torch, api, w.text, dtext, pats)
     if not a.skip_extra:
+        extra["fasta"] = bench_fasta(torch, api, w.text, dtext)
         del dtext
         torch.cuda.empty_cache()
         extra["degenerate"], extra["batched"] = bench_batched(torch, api, synth)

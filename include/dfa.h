@@ -110,6 +110,16 @@ int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
               void *workspace, int64_t workspace_bytes,
               const dfa_tune *tune, void *stream);
 
+/* Measurement hook for load-balance studies: dfa_count's count-only scan
+ * (n >= 1, no positions) where workgroup b also writes, for b < wg_cap,
+ * wg_times[3b] = its start and wg_times[3b+1] = its end on the device's
+ * constant-rate wall clock (hipDeviceAttributeWallClockRate) and
+ * wg_times[3b+2] = its length in shader cycles (device, 8-byte aligned).
+ * Returns the number of workgroups launched, or DFA_EINVAL / DFA_EHIP. */
+int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
+                        int64_t *count, unsigned long long *wg_times, int64_t wg_cap,
+                        const dfa_tune *tune, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched: many patterns over many texts in one launch.                    */
 /* ------------------------------------------------------------------------ */
@@ -284,7 +294,8 @@ int64_t dfa_fasta_workspace_bytes(int64_t n);
  * plain sequence: a line whose first byte is '>' is a header (it starts a
  * record; none of its bytes are kept); every other byte is kept except '
 '
- * and '', with 'a'..'z' made upper case (soft-masking dropped).
+ * and '
+', with 'a'..'z' made upper case (soft-masking dropped).
  *   out        device, room for n bytes: the kept bytes, in order
  *   rec_start  device int64, room for rec_cap entries: where each record's
  *              sequence starts in `out` (the first rec_cap records)

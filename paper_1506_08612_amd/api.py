@@ -94,6 +94,7 @@ SIGNATURES = {
     "dfa_build": (ctypes.c_int, [_vp, _i32, _vp]),
     "dfa_count_workspace_bytes": (_i64, [_i64, _i32, _i32, _TuneP]),
     "dfa_count": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP, _vp]),
+    "dfa_count_timed": (_i64, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _TuneP, _vp]),
     "dfa_batch_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
                                          _PlanP, _vp]),
     "dfa_batch_run": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _PlanP, _vp, _vp]),
@@ -228,6 +229,18 @@ def positions(text, table, m: int, cap: Optional[int] = None, t: Optional[Tune] 
     count_async(text, table, m, out, pos, cap, ws, t=t, stream=stream)
     c = int(out.item())
     return c, pos[:min(c, int(cap))]
+
+
+def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_cap: int = 1 << 22):
+    """Count-only scan that also records every workgroup's start/end (wall clock) and
+    cycles: returns (count, int64 array of shape (workgroups, 3)) (synchronises)."""
+    torch = _torch()
+    out = torch.empty(1, dtype=torch.int64, device=text.device)
+    times = torch.zeros(3 * wg_cap, dtype=torch.int64, device=text.device)
+    nb = _check(lib.dfa_count_timed(text.data_ptr(), text.numel(), table.data_ptr(), m, out.data_ptr(),
+                                    times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
+    k = min(nb, wg_cap)
+    return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
 
 
 # ---------------------------------------------------------------------------

@@ -65,6 +65,8 @@ struct ScanParams {
     const int64_t *walk_off;    // kPositions: output offset per walk
     int64_t *positions;         // kPositions
     int64_t cap;
+    unsigned long long *wg_times;  // measurement only (kCount): 3 words per workgroup, or null
+    int64_t wg_cap;                // workgroups with room in wg_times
 };
 
 // matches per walk whose end offsets the counting pass keeps (in the
@@ -174,6 +176,10 @@ template <int K, int LINE, int MODE, int H>
 __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
+    // measurement hook: the workgroup's start (constant-rate wall clock) and cycles
+    const bool timed = MODE == kCount && p.wg_times != nullptr && int64_t(blockIdx.x) < p.wg_cap;
+    const unsigned long long t_wall = timed ? wall_clock64() : 0ull;
+    const unsigned long long t_cyc = timed ? clock64() : 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     // wave index, known to the compiler as uniform so that per-wave addresses
     // live in scalar registers
@@ -342,6 +348,12 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
         unsigned long long sum = 0;
         for (int w = 0; w < nwaves; ++w) sum += red[w];
         if (sum) atomicAdd(p.total, sum);
+        if (timed) {
+            unsigned long long *t = p.wg_times + 3 * int64_t(blockIdx.x);
+            t[0] = t_wall;
+            t[1] = wall_clock64();
+            t[2] = clock64() - t_cyc;
+        }
     }
 }
 
@@ -787,4 +799,38 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     rc = launch_scan(pl, kPositions, sp, st);
     if (rc == DFA_OK) dfa::clear_error();
     return rc;
+}
+
+extern "C" int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m, int64_t *count,
+                                   unsigned long long *wg_times, int64_t wg_cap, const dfa_tune *tune, void *stream) {
+    if (n <= 0 || m < 1 || m > DFA_MAX_M || !text || !table || !count || wg_cap < 0 || (wg_cap > 0 && !wg_times)) {
+        dfa::set_error("dfa_count_timed: bad arguments");
+        return DFA_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(text) & 15) || (reinterpret_cast<uintptr_t>(table) & 3) ||
+        (reinterpret_cast<uintptr_t>(count) & 7) || (reinterpret_cast<uintptr_t>(wg_times) & 7)) {
+        dfa::set_error("dfa_count_timed: misaligned argument");
+        return DFA_EINVAL;
+    }
+    if (!check_tune(tune)) return DFA_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(count));
+    if (!hip_ok(hipGetLastError(), "k_zero_u64 launch")) return DFA_EHIP;
+    Plan pl;
+    if (!make_plan(n, m, kCount, tune, pl)) return DFA_EHIP;
+    ScanParams sp{};
+    sp.text = text;
+    sp.n = n;
+    sp.table = table;
+    sp.m = m;
+    sp.rounds = pl.rounds;
+    sp.S = pl.S;
+    sp.nwalks = pl.nwalks;
+    sp.total = reinterpret_cast<unsigned long long *>(count);
+    sp.wg_times = wg_times;
+    sp.wg_cap = wg_cap;
+    const int rc = launch_scan(pl, kCount, sp, st);
+    if (rc != DFA_OK) return rc;
+    dfa::clear_error();
+    return pl.blocks;
 }
