@@ -11,6 +11,11 @@ import os
 from typing import Optional, Sequence
 
 import numpy as np
+# torch ships its own HIP runtime (loaded under a different file name than the
+# system one libdfa names).  Importing torch first makes the library bind to
+# that same runtime by its soname: two HIP runtimes in one process do not share
+# the device, and the second to start reports that there is none.
+import torch  # noqa: F401  (load order)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdfa.so")

@@ -9,11 +9,6 @@ namespace dfa {
 void set_error(const char *fmt, ...);
 void clear_error();
 
-// Smallest text span one automaton walk owns by default.  The walk re-reads
-// m-1 bytes past its span (the overlap of Algorithm 1), so the span must be
-// long against m for that overhead to stay small.
-constexpr int64_t kMinChainBytes = 1024;
-
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

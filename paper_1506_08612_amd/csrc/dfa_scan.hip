@@ -61,7 +61,7 @@ struct ScanParams {
     int64_t nwalks;
     unsigned long long *total;  // kCount / kCountPerWalk: += matches
     uint32_t *walk_count;       // kCountPerWalk: matches per walk
-    uint32_t *walk_buf;         // kCountPerWalk: end offsets (within the walk) of its first kBuffered matches
+    uint16_t *walk_buf;         // kCountPerWalk: start offsets (within the walk) of its first kBuffered matches
     const int64_t *walk_off;    // kPositions: output offset per walk
     int64_t *positions;         // kPositions
     int64_t cap;
@@ -72,6 +72,9 @@ struct ScanParams {
 // matches per walk whose end offsets the counting pass keeps (in the
 // workspace); walks with more are walked again by the positions pass
 constexpr int kBuffered = 16;
+// buffered matches are kept as 16-bit start offsets within the walk (a walk
+// owns the starts of its span): the positions path needs S <= 65536
+constexpr int64_t kMaxPositionsSpan = 65536;
 
 __host__ __device__ inline int table_lds_bytes(int m) { return table_lds_rows_bytes(m + 1); }
 
@@ -79,16 +82,17 @@ struct WalkLane {
     int64_t wstart;  // first byte of the walk
     uint32_t len;    // bytes the walk reads (span + m - 1, clipped at the text end)
     uint32_t cnt;    // matches (per-walk counting pass)
-    uint32_t *buf;   // its kBuffered end offsets (per-walk counting pass)
+    uint16_t *buf;   // its kBuffered start offsets (per-walk counting pass)
     int64_t off;     // next output slot (positions pass)
 };
 
-// The end offsets of a lane's matches in one unit (hit mask from walk16_hits,
-// first byte in bit 15), in increasing order, into the walk's buffer.
-__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, WalkLane &w) {
+// The start offsets of a lane's matches in one unit (hit mask from
+// walk16_hits, first byte in bit 15; a match ending at byte j starts at
+// j - (m - 1)), in increasing order, into the walk's buffer.
+__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w) {
     while (hm) {
         const int b = 31 - __clz(hm);
-        if (w.cnt < uint32_t(kBuffered)) w.buf[w.cnt] = jb + uint32_t(15 - b);
+        if (w.cnt < uint32_t(kBuffered)) w.buf[w.cnt] = uint16_t(jb + uint32_t(15 - b) - (m - 1));
         ++w.cnt;
         hm ^= 1u << b;
     }
@@ -109,7 +113,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
     if constexpr (MODE == kCountPerWalk && !GUARD && K == 1) {
         uint32_t hm;
         walk16_hits(q[0], t[0], hm, m);
-        if (__ballot(hm != 0)) record_hits(hm, jb, wl[0]);
+        if (__ballot(hm != 0)) record_hits(hm, jb, m, wl[0]);
         return;
     }
 #pragma unroll
@@ -127,7 +131,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
                     add_hits(acc, hit);
                 } else if (MODE == kCountPerWalk) {
                     if (hit) {
-                        if (wl[s].cnt < uint32_t(kBuffered)) wl[s].buf[wl[s].cnt] = j;
+                        if (wl[s].cnt < uint32_t(kBuffered)) wl[s].buf[wl[s].cnt] = uint16_t(j - (m - 1));
                         ++wl[s].cnt;
                     }
                 } else if (hit) {
@@ -172,8 +176,16 @@ __device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q
 // registers free (one more wave per SIMD).
 constexpr int halo_units_for(int m) { return m <= 17 ? 1 : 4; }
 
+// The default counting kernels (one walk per lane, 64-byte rounds) are asked
+// to fit 6 waves per SIMD (at most 80 registers): the per-walk counting pass
+// with 4 overlap units would otherwise need 81 (the compiler then keeps one
+// overlap unit in scratch between the first round and the end of the walk).
+template <int K, int LINE, int MODE>
+constexpr int scan_waves_per_eu() { return (K == 1 && LINE == 64 && MODE != kPositions) ? 6 : 1; }
+
 template <int K, int LINE, int MODE, int H>
-__global__ __launch_bounds__(512) void k_scan(ScanParams p) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<K, LINE, MODE>())))
+void k_scan(ScanParams p) {
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     // measurement hook: the workgroup's start (constant-rate wall clock) and cycles
@@ -187,6 +199,29 @@ __global__ __launch_bounds__(512) void k_scan(ScanParams p) {
     const int nwaves = blockDim.x / kWave;
     // table first (LDS address 0), then one transpose buffer per wave
     v4u *xb = reinterpret_cast<v4u *>(smem + table_lds_bytes(p.m) + wave * (K * kWave * LINE));
+
+    if (MODE == kPositions) {
+        // only walks whose matches did not all fit the counting pass's buffer
+        // are walked again: a workgroup without any leaves before loading the
+        // table.  The vote goes through the first word of each wave's
+        // transpose buffer (no static LDS: the table must start at address 0).
+        const int64_t gw0 = (int64_t(blockIdx.x) * nwaves + wave) * (kWave * K);
+        bool mine = false;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int64_t g = gw0 + s * kWave + lane;
+            mine |= g < p.nwalks && p.walk_count[g] > uint32_t(kBuffered);
+        }
+        const bool wave_has = __ballot(mine) != 0;
+        uint32_t *vote = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(p.m));
+        const int stride = K * kWave * LINE / 4;  // words per wave buffer
+        if (lane == 0) vote[wave * stride] = wave_has ? 1u : 0u;
+        __syncthreads();
+        bool any = false;
+        for (int w = 0; w < nwaves; ++w) any |= vote[w * stride] != 0;
+        if (!any) return;  // uniform over the workgroup
+        // the table load below ends with a barrier before any buffer is restaged
+    }
 
     // table -> LDS, rows padded to kRow bytes
     {
@@ -413,17 +448,40 @@ __global__ __launch_bounds__(kScanThreads) void k_walk_sums(const uint32_t *cnt,
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-// one block: exclusive scan of the nb block totals; total match count to *count
-__global__ __launch_bounds__(kScanThreads) void k_scan_parts(unsigned long long *part, int64_t nb,
-                                                             int64_t *count) {
-    __shared__ unsigned long long sh[kScanThreads / kWave];
+// one block: exclusive scan of the nb block totals; total match count to *count.
+// Each thread first sums kPartsPerThread consecutive totals, so one pass of the
+// block covers 1024 x 8 of them.
+constexpr int kPartsThreads = 1024;
+constexpr int kPartsPerThread = 8;
+
+__global__ __launch_bounds__(kPartsThreads) void k_scan_parts(unsigned long long *part, int64_t nb,
+                                                              int64_t *count) {
+    __shared__ unsigned long long sh[kPartsThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     unsigned long long carry = 0;
-    for (int64_t base = 0; base < nb; base += kScanThreads) {
-        const int64_t i = base + threadIdx.x;
-        const unsigned long long v = i < nb ? part[i] : 0;
-        unsigned long long tot;
-        const unsigned long long ex = block_exclusive_scan(v, sh, &tot);
-        if (i < nb) part[i] = ex + carry;
+    for (int64_t base = 0; base < nb; base += int64_t(kPartsThreads) * kPartsPerThread) {
+        const int64_t i0 = base + int64_t(threadIdx.x) * kPartsPerThread;
+        unsigned long long v[kPartsPerThread], mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPartsPerThread; ++k) {
+            v[k] = i0 + k < nb ? part[i0 + k] : 0ull;
+            mine += v[k];
+        }
+        const unsigned long long inc = wave_inclusive_scan(mine);
+        if (lane == kWave - 1) sh[w] = inc;
+        __syncthreads();
+        unsigned long long before = 0, tot = 0;
+        for (int k = 0; k < kPartsThreads / kWave; ++k) {
+            if (k < w) before += sh[k];
+            tot += sh[k];
+        }
+        __syncthreads();
+        unsigned long long run = carry + before + inc - mine;
+#pragma unroll
+        for (int k = 0; k < kPartsPerThread; ++k) {
+            if (i0 + k < nb) part[i0 + k] = run;
+            run += v[k];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) *count = int64_t(carry);
@@ -463,11 +521,11 @@ __global__ __launch_bounds__(kScanThreads) void k_walk_offsets(const uint32_t *c
 }
 
 // Positions of the walks with 1..kBuffered matches, from the counting pass's
-// buffer: start = walk start + end offset - (m - 1).  One block per 256 walks
+// buffer: start = walk start + buffered start offset.  One block per 256 walks
 // enumerates the block's buffered matches in order (a scan of the buffered
 // counts in LDS) so that consecutive threads write consecutive positions;
 // the slots of walks with more matches are left to the positions pass.
-__global__ __launch_bounds__(kScanThreads) void k_scatter_buffered(const uint32_t *walk_count, const uint32_t *walk_buf,
+__global__ __launch_bounds__(kScanThreads) void k_scatter_buffered(const uint32_t *walk_count, const uint16_t *walk_buf,
                                                                    const int64_t *walk_off, int64_t nwalks, int64_t S,
                                                                    int32_t m, int64_t *positions, int64_t cap) {
     __shared__ unsigned long long sh[kScanThreads / kWave];
@@ -497,7 +555,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_buffered(const uint32_
         const uint32_t i = k - first[lo];
         const int64_t dst = out[lo] + i;
         const int64_t gw = g0 + lo;
-        if (dst < cap) positions[dst] = gw * S + int64_t(walk_buf[gw * kBuffered + i]) - (m - 1);
+        if (dst < cap) positions[dst] = gw * S + int64_t(walk_buf[gw * kBuffered + i]);
     }
 }
 
@@ -537,9 +595,16 @@ size_t scan_lds_bytes(int wpg, int K, int line, int m) {
     return size_t(wpg) * K * kWave * line + size_t(table_lds_bytes(m));
 }
 
-int64_t min_span(const dfa_tune *t) {
-    return (t && t->chain_bytes > 0) ? t->chain_bytes : dfa::kMinChainBytes;
-}
+// Default span of one walk: 8 m rounded up to whole lines, at least 512 and
+// at most 2048 bytes.  Short walks make short workgroups, which the hardware
+// dispatcher balances well (the launch's tail, while the last workgroups
+// finish, shrinks with them); the span stays long against m so that the
+// overlap (m - 1 bytes walked twice) stays small.
+constexpr int64_t kSpanMin = 512;
+constexpr int64_t kSpanMax = 2048;
+
+// The shortest span a plan for this tune can use (sizes the positions workspace).
+int64_t min_span(const dfa_tune *t) { return (t && t->chain_bytes > 0) ? t->chain_bytes : kSpanMin; }
 
 // gfx950 compute unit: 4 SIMDs, 512 vector registers per lane per SIMD, at
 // most 8 waves per SIMD, 160 KiB of LDS
@@ -552,12 +617,6 @@ constexpr int kDefaultK = 1;
 constexpr int kDefaultLine = 64;
 constexpr int kDefaultWpg = 4;
 
-// Default span of one walk.  Many short walks (far more workgroups than fit
-// on the device at once) let the hardware dispatcher balance the load; the
-// span stays long against m so that the overlap (m-1 bytes walked twice) and
-// the per-workgroup table load stay small: 1 KiB up to m = 32, 2 KiB above.
-constexpr int64_t kSpanShort = 1024;
-constexpr int64_t kSpanLong = 2048;
 
 bool check_tune(const dfa_tune *t) {
     if (!t) return true;
@@ -602,7 +661,7 @@ bool check_tune(const dfa_tune *t) {
 int64_t max_walks(int64_t n, const dfa_tune *t) { return n > 0 ? dfa::ceil_div(n, min_span(t)) : 0; }
 
 // workspace layout: walk counts u32[nw] | walk offsets i64[nw] | block
-// partials u64[nb] | buffered match ends u32[nw * kBuffered]
+// partials u64[nb] | buffered match ends u16[nw * kBuffered]
 struct WsLayout {
     int64_t cnt = 0, off = 0, part = 0, buf = 0, total = 0;
 };
@@ -614,7 +673,7 @@ WsLayout ws_layout(int64_t nw) {
     L.off = L.cnt + dfa::round_up(nw * 4, 256);
     L.part = L.off + dfa::round_up(nw * 8, 256);
     L.buf = L.part + dfa::round_up(nb * 8, 256);
-    L.total = L.buf + dfa::round_up(nw * 4 * kBuffered, 256);
+    L.total = L.buf + dfa::round_up(nw * 2 * kBuffered, 256);
     return L;
 }
 int64_t workspace_for(int64_t nw) { return ws_layout(nw).total; }
@@ -633,24 +692,24 @@ int kernel_vgprs(const void *fn) {
     return regs;
 }
 
-// Default waves per workgroup: the smallest of 2, 4, 8 whose workgroups keep
+// Default waves per workgroup: the smaller of 4 and 8 whose workgroups keep
 // at least 90% of the waves a CU can hold by registers resident, given the
 // LDS each one needs (its transpose buffers plus its own copy of the table).
-// Small workgroups refill a CU at a finer grain; large ones share one table
+// Smaller workgroups refill a CU at a finer grain; larger ones share one table
 // among more waves, which matters once the table is large (long patterns).
 int default_wpg(const void *fn, int K, int line, int m) {
     const int regs = kernel_vgprs(fn);
     if (regs <= 0) return kDefaultWpg;
     const int per_simd = std::min(kMaxWavesPerSimd, kVgprsPerLane / int(dfa::round_up(regs, 8)));
     const int by_regs = kSimdsPerCu * std::max(1, per_simd);
-    int waves[3], best = 0;
-    const int cand[3] = {2, 4, 8};
-    for (int i = 0; i < 3; ++i) {
+    int waves[2], best = 0;
+    const int cand[2] = {4, 8};
+    for (int i = 0; i < 2; ++i) {
         const int groups = int(kLdsPerCu / scan_lds_bytes(cand[i], K, line, m));
         waves[i] = std::min(by_regs, groups * cand[i]);
         best = std::max(best, waves[i]);
     }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (10 * waves[i] >= 9 * best) return cand[i];
     return kDefaultWpg;
 }
@@ -674,7 +733,7 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
         // multiple of the line makes every round straddle two lines; with
         // hundreds of streaming waves per XCD the shared line is evicted from
         // L2 before the next round needs it, and HBM reads double.
-        pl.S = dfa::round_up(m <= 32 ? kSpanShort : kSpanLong, 128);
+        pl.S = std::min<int64_t>(kSpanMax, std::max<int64_t>(kSpanMin, dfa::round_up(int64_t(8) * m, 128)));
     }
     pl.rounds = int(dfa::ceil_div(pl.S + m - 1, pl.line));
     pl.nwalks = n > 0 ? dfa::ceil_div(n, pl.S) : 0;
@@ -755,6 +814,10 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
 
     Plan pl;
     if (!make_plan(n, m, want_pos ? kCountPerWalk : kCount, tune, pl)) return DFA_EHIP;
+    if (want_pos && pl.S > kMaxPositionsSpan) {
+        dfa::set_error("dfa_count: positions need chain_bytes <= %lld", (long long)kMaxPositionsSpan);
+        return DFA_EINVAL;
+    }
 
     ScanParams sp{};
     sp.text = text;
@@ -780,18 +843,18 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     uint32_t *wcnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
     int64_t *woff = reinterpret_cast<int64_t *>(ws + L.off);
     unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + L.part);
-    uint32_t *wbuf = reinterpret_cast<uint32_t *>(ws + L.buf);
+    uint16_t *wbuf = reinterpret_cast<uint16_t *>(ws + L.buf);
 
     sp.walk_count = wcnt;
     sp.walk_buf = wbuf;
     int rc = launch_scan(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
     hipLaunchKernelGGL(k_walk_sums, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw, part);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, st, part, nb, count);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, part, nb, count);
     hipLaunchKernelGGL(k_walk_offsets, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw,
                        (const unsigned long long *)part, woff);
     hipLaunchKernelGGL(k_scatter_buffered, dim3(unsigned(dfa::ceil_div(nw, kScanThreads))), dim3(kScanThreads), 0, st,
-                       (const uint32_t *)wcnt, (const uint32_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions,
+                       (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions,
                        cap);
     if (!hip_ok(hipGetLastError(), "prefix-sum launch")) return DFA_EHIP;
     sp.walk_off = woff;

@@ -10,6 +10,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -204,3 +205,17 @@ def test_batch_plan_rejects_bad_arguments():
     assert api.lib.dfa_batch_run(fake, 50, fake, 4096, fake, ctypes.byref(plan), fake, None) == api.DFA_EINVAL
     # tables buffer shorter than the tables the plan refers to
     assert api.lib.dfa_batch_run(fake, 100, fake, 1000, fake, ctypes.byref(plan), fake, None) == api.DFA_EINVAL
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must still leave one HIP runtime mapped:
+    torch's copy and the system's are distinct files, and a second runtime in the
+    process sees no device."""
+    code = ("from paper_1506_08612_amd import api\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
