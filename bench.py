@@ -9,11 +9,16 @@ dfa_count with sorted positions (count + every match start).  `value` is text
 bytes scanned per second over the timed steps (5 x 3.2e9 bytes per step).
 
 Also reported:
-* roofline -- the scan kernel alone: count-only dfa_count launches bracketed by
-  HIP events on the launch stream; algorithmic bytes = the text read once;
+* roofline -- the step's dominant kernel, its walk over the whole text (the
+  per-walk counting pass of count + positions), bracketed by HIP events on the
+  launch stream (dfa_set_scan_events) in every call of a second run of the
+  same steps right after the timed one (an event between two launches leaves
+  the stream idle for ~10-15 us, so the timed steps carry none); algorithmic
+  bytes = the text read once; the count-only scan is timed beside it;
 * cpu_baseline -- the CPU oracle (plain C, one thread) timed on a bounded
   prefix of the same text for the same five patterns;
-* per-pattern latency p50/p99 of the full call over the timed steps;
+* per-pattern latency p50/p99 of the full call (events around each call, in the
+  second run of the steps);
 * batched -- 1 GB GC-41% text x 1024 patterns (lengths 4..64, half drawn from
   the text) with merged multi-pattern automata in one launch (autotuned
   automaton budget and shape, replayed from a HIP graph) against the same GPU
@@ -51,7 +56,7 @@ METRIC = "text GB/s (and % of HBM peak) single-pattern; pattern-bytes/s batched;
 HBM_PEAK_GBS = 8000.0
 PATTERN_LENGTHS = (4, 8, 16, 32, 64)
 SCAN_SOURCES = [os.path.join(ROOT, "paper_1506_08612_amd", "csrc", f) for f in ("dfa_scan.hip", "walk_common.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_count_genome3200MB_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_perwalk_genome3200MB_traffic.txt")
 
 
 def log(*a):
@@ -391,30 +396,43 @@ def main(argv=None) -> int:
         tab_dev.copy_(tab_pinned, non_blocking=True)
         copied.record(stream)
         for i, p in enumerate(pats):
-            if events is not None:
-                events[i][0].record(stream)
             tab = tab_dev[tab_offs[i]:tab_offs[i] + tab_sizes[i]]
-            api.count_async(dtext, tab, len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws,
-                            stream=stream)
-            if events is not None:
-                events[i][1].record(stream)
+            if events is None:
+                api.count_async(dtext, tab, len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws, stream=stream)
+                continue
+            e0, e1, w0, w1 = events[i]
+            e0.record(stream)
+            with api.ScanEvents(w0, w1, stream):
+                api.count_async(dtext, tab, len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws, stream=stream)
+            e1.record(stream)
 
     for _ in range(a.warmup):
         one_step()
     torch.cuda.synchronize()
 
-    lat = [[] for _ in pats]
     t0 = time.perf_counter()
-    ev_all = []
     for _ in range(a.steps):
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in pats]
-        one_step(evs)
-        ev_all.append(evs)
+        one_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+
+    # the same steps again, each call and each text walk bracketed by events
+    lat = [[] for _ in pats]
+    walk_ms = [[] for _ in pats]
+    ev_all = [[tuple(torch.cuda.Event(enable_timing=True) for _ in range(4)) for _ in pats]
+              for _ in range(a.steps)]
+    for evs in ev_all:  # create the event handles first
+        for ev in evs:
+            for e in ev:
+                e.record(stream)
+    torch.cuda.synchronize()
     for evs in ev_all:
-        for i, (e0, e1) in enumerate(evs):
+        one_step(evs)
+    torch.cuda.synchronize()
+    for evs in ev_all:
+        for i, (e0, e1, w0, w1) in enumerate(evs):
             lat[i].append(e0.elapsed_time(e1))
+            walk_ms[i].append(w0.elapsed_time(w1))
     got = [int(c.item()) for c in cnt_bufs]
     assert got == counts, (got, counts)
 
@@ -434,8 +452,9 @@ def main(argv=None) -> int:
         e1.record(stream)
         torch.cuda.synchronize()
         kern[len(p)] = e0.elapsed_time(e1) / a.kernel_reps
-    avg_kernel_ms = float(np.mean(list(kern.values())))
-    achieved = n / (avg_kernel_ms * 1e-3) / 1e9
+    count_only_gbs = n / (float(np.mean(list(kern.values()))) * 1e-3) / 1e9
+    walk_avg_ms = float(np.mean([x for w in walk_ms for x in w]))
+    achieved = n / (walk_avg_ms * 1e-3) / 1e9
     traffic = read_traffic()
 
     if a.copy_calibration > 0:
@@ -511,10 +530,12 @@ def main(argv=None) -> int:
                        "p99": round(float(np.percentile(lat_all, 99)), 4),
                        "per_pattern_p50": {str(len(p)): round(float(np.percentile(lat[i], 50)), 4)
                                            for i, p in enumerate(pats)}},
+        "walk_kernel_ms": {str(len(p)): round(float(np.mean(walk_ms[i])), 4) for i, p in enumerate(pats)},
         "count_only_kernel_ms": {str(k): round(v, 4) for k, v in kern.items()},
+        "count_only_frac": round(count_only_gbs / HBM_PEAK_GBS, 4),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_scan (count-only automaton walk)",
+            "kernel": "k_scan per-walk counting pass (the text walk of count + positions)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

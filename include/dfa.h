@@ -110,6 +110,16 @@ int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
               void *workspace, int64_t workspace_bytes,
               const dfa_tune *tune, void *stream);
 
+/* Measurement hook for per-kernel timing: while set, every dfa_count call
+ * made from the calling thread records `begin` on its stream right before
+ * the launch of its walk over the whole text (the count-only scan, or with
+ * positions the per-walk counting pass) and `end` right after it, so that
+ * the two events bracket that one kernel.  Both are hipEvent_t handles the
+ * caller created (with timing); NULL, NULL clears the hook.  A dfa_count
+ * that fails before that launch records neither.  Returns DFA_OK, or
+ * DFA_EINVAL if exactly one of the two is NULL. */
+int dfa_set_scan_events(void *begin, void *end);
+
 /* Measurement hook for load-balance studies: dfa_count's count-only scan
  * (n >= 1, no positions) where workgroup b also writes, for b < wg_cap,
  * wg_times[3b] = its start and wg_times[3b+1] = its end on the device's

@@ -100,6 +100,7 @@ SIGNATURES = {
     "dfa_count_workspace_bytes": (_i64, [_i64, _i32, _i32, _TuneP]),
     "dfa_count": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP, _vp]),
     "dfa_count_timed": (_i64, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _TuneP, _vp]),
+    "dfa_set_scan_events": (ctypes.c_int, [_vp, _vp]),
     "dfa_batch_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
                                          _PlanP, _vp]),
     "dfa_batch_run": (ctypes.c_int, [_vp, _i64, _vp, _i64, _vp, _PlanP, _vp, _vp]),
@@ -246,6 +247,28 @@ def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_c
                                     times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
     k = min(nb, wg_cap)
     return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
+
+
+class ScanEvents:
+    """Context manager: while active, every dfa_count call from this thread records
+    `begin` / `end` (torch.cuda.Event with timing) around its walk over the whole text,
+    so that begin.elapsed_time(end) is that one kernel's duration."""
+
+    def __init__(self, begin, end, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        for e in (begin, end):
+            if not e.cuda_event:  # torch creates the handle on the first record
+                e.record(s)
+        self.handles = (begin.cuda_event, end.cuda_event)
+
+    def __enter__(self):
+        _check(lib.dfa_set_scan_events(*self.handles))
+        return self
+
+    def __exit__(self, *exc):
+        _check(lib.dfa_set_scan_events(None, None))
+        return False
 
 
 # ---------------------------------------------------------------------------

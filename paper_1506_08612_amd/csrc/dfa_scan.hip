@@ -59,10 +59,12 @@ struct ScanParams {
     int32_t rounds;    // ceil((S + m - 1) / LINE)
     int64_t S;         // span bytes per walk (multiple of 16)
     int64_t nwalks;
-    unsigned long long *total;  // kCount / kCountPerWalk: += matches
-    uint32_t *walk_count;       // kCountPerWalk: matches per walk
-    uint16_t *walk_buf;         // kCountPerWalk: start offsets (within the walk) of its first kBuffered matches
-    const int64_t *walk_off;    // kPositions: output offset per walk
+    unsigned long long *total;    // kCount: += matches
+    uint32_t *walk_count;         // kCountPerWalk: matches per walk (read back by kPositions)
+    uint16_t *walk_buf;           // kCountPerWalk: start offsets (within the walk) of its first kBuffered matches
+    unsigned long long *wg_part;  // kCountPerWalk: matches per workgroup
+    const uint32_t *wg_flag;      // kPositions: nonzero for a workgroup with a walk past its buffer
+    const int64_t *walk_off;      // kPositions: output offset per walk (walks past their buffer only)
     int64_t *positions;         // kPositions
     int64_t cap;
     unsigned long long *wg_times;  // measurement only (kCount): 3 words per workgroup, or null
@@ -82,17 +84,23 @@ struct WalkLane {
     int64_t wstart;  // first byte of the walk
     uint32_t len;    // bytes the walk reads (span + m - 1, clipped at the text end)
     uint32_t cnt;    // matches (per-walk counting pass)
-    uint16_t *buf;   // its kBuffered start offsets (per-walk counting pass)
     int64_t off;     // next output slot (positions pass)
 };
+
+// The buffer of walk s of this lane: p.walk_buf points at the wave's first
+// walk in the per-walk counting pass, so the lane's own part of it follows
+// from the lane index alone (no pointer held per lane).
+__device__ __forceinline__ uint16_t *walk_slots(const ScanParams &p, int s) {
+    return p.walk_buf + (s * kWave + int(__lane_id())) * kBuffered;
+}
 
 // The start offsets of a lane's matches in one unit (hit mask from
 // walk16_hits, first byte in bit 15; a match ending at byte j starts at
 // j - (m - 1)), in increasing order, into the walk's buffer.
-__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w) {
+__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, uint16_t *buf) {
     while (hm) {
         const int b = 31 - __clz(hm);
-        if (w.cnt < uint32_t(kBuffered)) w.buf[w.cnt] = uint16_t(jb + uint32_t(15 - b) - (m - 1));
+        if (w.cnt < uint32_t(kBuffered)) buf[w.cnt] = uint16_t(jb + uint32_t(15 - b) - (m - 1));
         ++w.cnt;
         hm ^= 1u << b;
     }
@@ -111,9 +119,30 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
         return;
     }
     if constexpr (MODE == kCountPerWalk && !GUARD && K == 1) {
+        // Each wave picks per unit how to walk it.  While its last unit had no
+        // match it walks like the count-only scan (one wave-wide count in a
+        // scalar register) and walks the unit again, from the state it started
+        // in, with per-lane hit masks only if that count is nonzero; after a
+        // unit with matches it walks the next one with hit masks directly.
+        // `acc` carries the choice (nonzero: hit masks); the per-walk counts
+        // live in wl and `acc` is rewritten with their sum at the end.
         uint32_t hm;
-        walk16_hits(q[0], t[0], hm, m);
-        if (__ballot(hm != 0)) record_hits(hm, jb, m, wl[0]);
+        if (__builtin_amdgcn_readfirstlane(acc)) {
+            walk16_hits(q[0], t[0], hm, m);
+            const bool any = __ballot(hm != 0) != 0;
+            if (any) record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+            acc = any ? 1u : 0u;
+        } else {
+            const uint32_t q0 = q[0];
+            uint32_t a = 0;
+            walk16_count(q[0], t[0], a, m);
+            if (__builtin_amdgcn_readfirstlane(a)) {
+                q[0] = q0;
+                walk16_hits(q[0], t[0], hm, m);
+                record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+                acc = 1u;
+            }
+        }
         return;
     }
 #pragma unroll
@@ -131,7 +160,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
                     add_hits(acc, hit);
                 } else if (MODE == kCountPerWalk) {
                     if (hit) {
-                        if (wl[s].cnt < uint32_t(kBuffered)) wl[s].buf[wl[s].cnt] = uint16_t(j - (m - 1));
+                        if (wl[s].cnt < uint32_t(kBuffered)) walk_slots(p, s)[wl[s].cnt] = uint16_t(j - (m - 1));
                         ++wl[s].cnt;
                     }
                 } else if (hit) {
@@ -140,6 +169,29 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
                 }
             }
         }
+    }
+}
+
+// One overlap unit on the whole-wave path, where every walk of the wave reads
+// the same number of overlap bytes: `nvalid` (1..16, wave-uniform) of its 16
+// bytes belong to the walk.  With one walk per lane and a counting mode the
+// 16 steps run as in the span and the hit mask drops the bytes past the
+// overlap (the count-only mode adds the lane's hits to `extra`, summed over
+// the wave at the end); otherwise the byte loop with its length check.
+template <int K, int MODE>
+__device__ __forceinline__ void walk_overlap_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
+                                                  uint32_t nvalid, uint32_t &acc, uint32_t &extra,
+                                                  WalkLane (&wl)[K], const ScanParams &p) {
+    if constexpr (K == 1 && MODE != kPositions) {
+        uint32_t hm;
+        walk16_hits(q[0], t[0], hm, m);
+        hm &= 0xffffu & ~((1u << (16u - nvalid)) - 1u);  // byte i of the unit is bit 15 - i
+        if (MODE == kCount)
+            extra += uint32_t(__popc(hm));
+        else if (__ballot(hm != 0))
+            record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+    } else {
+        walk_unit<K, MODE, true>(t, q, m, jb, acc, wl, p);
     }
 }
 
@@ -171,10 +223,11 @@ __device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q
     }
 }
 
-// Overlap units loaded ahead (H): 1 unit covers m <= 17, 4 units m <= 65.
-// The kernel is instantiated for both so that short patterns keep 12 more
-// registers free (one more wave per SIMD).
-constexpr int halo_units_for(int m) { return m <= 17 ? 1 : 4; }
+// Overlap units loaded ahead (H): 1 unit covers m <= 17, 2 units m <= 33,
+// 4 units m <= 65.  Every unit held costs 4 registers for the whole walk, so
+// the default shape (one walk per lane, 64-byte rounds) is instantiated for
+// all three and the others for 1 and 4.
+constexpr int halo_units_for(int m) { return m <= 17 ? 1 : m <= 33 ? 2 : 4; }
 
 // The default counting kernels (one walk per lane, 64-byte rounds) are asked
 // to fit 6 waves per SIMD (at most 80 registers): the per-walk counting pass
@@ -185,7 +238,7 @@ constexpr int scan_waves_per_eu() { return (K == 1 && LINE == 64 && MODE != kPos
 
 template <int K, int LINE, int MODE, int H>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<K, LINE, MODE>())))
-void k_scan(ScanParams p) {
+void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.walk_buf to its wave
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     // measurement hook: the workgroup's start (constant-rate wall clock) and cycles
@@ -200,28 +253,9 @@ void k_scan(ScanParams p) {
     // table first (LDS address 0), then one transpose buffer per wave
     v4u *xb = reinterpret_cast<v4u *>(smem + table_lds_bytes(p.m) + wave * (K * kWave * LINE));
 
-    if (MODE == kPositions) {
-        // only walks whose matches did not all fit the counting pass's buffer
-        // are walked again: a workgroup without any leaves before loading the
-        // table.  The vote goes through the first word of each wave's
-        // transpose buffer (no static LDS: the table must start at address 0).
-        const int64_t gw0 = (int64_t(blockIdx.x) * nwaves + wave) * (kWave * K);
-        bool mine = false;
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int64_t g = gw0 + s * kWave + lane;
-            mine |= g < p.nwalks && p.walk_count[g] > uint32_t(kBuffered);
-        }
-        const bool wave_has = __ballot(mine) != 0;
-        uint32_t *vote = reinterpret_cast<uint32_t *>(smem + table_lds_bytes(p.m));
-        const int stride = K * kWave * LINE / 4;  // words per wave buffer
-        if (lane == 0) vote[wave * stride] = wave_has ? 1u : 0u;
-        __syncthreads();
-        bool any = false;
-        for (int w = 0; w < nwaves; ++w) any |= vote[w * stride] != 0;
-        if (!any) return;  // uniform over the workgroup
-        // the table load below ends with a barrier before any buffer is restaged
-    }
+    // only walks whose matches did not all fit the counting pass's buffer are
+    // walked again: a workgroup without any leaves before loading the table
+    if (MODE == kPositions && p.wg_flag[blockIdx.x] == 0) return;
 
     // table -> LDS, rows padded to kRow bytes
     {
@@ -233,6 +267,7 @@ void k_scan(ScanParams p) {
     __syncthreads();
 
     const int64_t g0 = (int64_t(blockIdx.x) * nwaves + wave) * (kWave * K);
+    if (MODE == kCountPerWalk) p.walk_buf += g0 * kBuffered;
     const uint32_t m = uint32_t(p.m);
     const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(p.S) + 16u * uint32_t(lane % G::U);
 
@@ -253,7 +288,6 @@ void k_scan(ScanParams p) {
         wl[s].len = uint32_t(len);
         wl[s].cnt = 0;
         wl[s].off = 0;
-        wl[s].buf = MODE == kCountPerWalk ? p.walk_buf + g * kBuffered : nullptr;
         q[s] = 0;
         if (MODE == kPositions) {
             // only walks whose matches did not all fit the counting pass's buffer
@@ -333,13 +367,15 @@ void k_scan(ScanParams p) {
         }
         // the overlap, from registers, then (m > 65) the rest of it from memory
         const uint32_t hb = uint32_t(p.S);
+        uint32_t extra = 0;
 #pragma unroll
         for (int u = 0; u < H; ++u) {
             if (u < hu) {
                 v4u t[K];
 #pragma unroll
                 for (int s = 0; s < K; ++s) t[s] = halo[s][u];
-                walk_unit<K, MODE, true>(t, q, m, hb + 16u * u, acc, wl, p);
+                const uint32_t nv = m - 1 - 16u * u;
+                walk_overlap_unit<K, MODE>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
             }
         }
         for (int u = H; u < hu; ++u) {
@@ -347,7 +383,15 @@ void k_scan(ScanParams p) {
 #pragma unroll
             for (int s = 0; s < K; ++s)
                 t[s] = *reinterpret_cast<const v4u *>(p.text + (g0 + s * kWave + lane + 1) * p.S + 16 * u);
-            walk_unit<K, MODE, true>(t, q, m, hb + 16u * u, acc, wl, p);
+            const uint32_t nv = m - 1 - 16u * u;
+            walk_overlap_unit<K, MODE>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
+        }
+        if (MODE == kCount && K == 1) {
+            // the overlap's hits, summed over the wave
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) extra += uint32_t(__shfl_xor(int(extra), o));
+            acc = uint32_t(__builtin_amdgcn_readfirstlane(int(acc))) +
+                  uint32_t(__builtin_amdgcn_readfirstlane(int(extra)));
         }
     } else {
         v4u pf[K][G::U];
@@ -374,7 +418,8 @@ void k_scan(ScanParams p) {
         for (int o = kWave / 2; o > 0; o >>= 1) c += uint32_t(__shfl_xor(int(c), o));
         acc = uint32_t(__builtin_amdgcn_readfirstlane(int(c)));
     }
-    // workgroup sum in LDS (reusing the first transpose buffer), one atomic
+    // workgroup sum in LDS (reusing the first transpose buffer): one atomic,
+    // or (per-walk counting) the workgroup's total for the placement scan
     unsigned long long *red = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(p.m));
     __syncthreads();
     if (lane == 0) red[wave] = acc;
@@ -382,7 +427,10 @@ void k_scan(ScanParams p) {
     if (threadIdx.x == 0) {
         unsigned long long sum = 0;
         for (int w = 0; w < nwaves; ++w) sum += red[w];
-        if (sum) atomicAdd(p.total, sum);
+        if (MODE == kCountPerWalk)
+            p.wg_part[blockIdx.x] = sum;
+        else if (sum)
+            atomicAdd(p.total, sum);
         if (timed) {
             unsigned long long *t = p.wg_times + 3 * int64_t(blockIdx.x);
             t[0] = t_wall;
@@ -393,15 +441,19 @@ void k_scan(ScanParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-walk offsets and the buffered positions.  Blocks of 256 threads; every
-// global access is a coalesced pass over consecutive walks, staged in LDS.
+// Placement of the positions.  The counting pass leaves, per walk, its match
+// count and the start offsets of its first kBuffered matches, and per
+// workgroup its total.  One scan of the workgroup totals gives every
+// workgroup's first output slot; then one block per counting workgroup (one
+// thread per walk) scans its walks' counts, writes the buffered positions in
+// order, the output offsets of the walks with more matches than the buffer
+// holds, and whether the workgroup has any: the positions pass walks only
+// those workgroups again.
 // ---------------------------------------------------------------------------
 
 __global__ void k_zero_u64(unsigned long long *x) { *x = 0; }
 
-constexpr int kScanThreads = 256;
-constexpr int kScanPerThread = 4;
-constexpr int kScanBlock = kScanThreads * kScanPerThread;  // walks per block of the offset passes
+constexpr int kMaxGroupWalks = 1024;  // walks of one counting workgroup: 8 waves x 64 lanes x 2 walks
 
 __device__ __forceinline__ unsigned long long wave_inclusive_scan(unsigned long long v) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -413,17 +465,18 @@ __device__ __forceinline__ unsigned long long wave_inclusive_scan(unsigned long 
     return v;
 }
 
-// Exclusive scan of one value per thread over a 256-thread block; `sh` holds
-// 4 scratch slots in LDS; *total receives the block total.
+// Exclusive scan of one value per thread over the block (any multiple of 64
+// threads up to 1024); `sh` holds 16 scratch slots in LDS; *total receives
+// the block total.
 __device__ __forceinline__ unsigned long long block_exclusive_scan(unsigned long long v, unsigned long long *sh,
                                                                    unsigned long long *total) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
     const unsigned long long inc = wave_inclusive_scan(v);
     if (lane == kWave - 1) sh[w] = inc;
     __syncthreads();
     unsigned long long before = 0, all = 0;
-#pragma unroll
-    for (int i = 0; i < kScanThreads / kWave; ++i) {
+    for (int i = 0; i < nw; ++i) {
         if (i < w) before += sh[i];
         all += sh[i];
     }
@@ -432,122 +485,150 @@ __device__ __forceinline__ unsigned long long block_exclusive_scan(unsigned long
     return before + inc - v;
 }
 
-// part[b] = matches of the walks of block b
-__global__ __launch_bounds__(kScanThreads) void k_walk_sums(const uint32_t *cnt, int64_t nw,
-                                                            unsigned long long *part) {
-    __shared__ unsigned long long sh[kScanThreads / kWave];
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
-    unsigned long long v = 0;
+// Output slots are handed out in two levels: the workgroup totals fall in
+// super-blocks of kSuper consecutive workgroups; one block sums every
+// super-block and scans those sums, and each placement block adds the totals
+// of the workgroups before its own inside its super-block.  Every kernel
+// here synchronises its block a fixed number of times, whatever the text size.
+constexpr int kSuper = 1024;
+constexpr int kPartsThreads = 1024;
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int64_t g = base + i * kScanThreads + threadIdx.x;
-        if (g < nw) v += cnt[g];
-    }
-    unsigned long long total;
-    block_exclusive_scan(v, sh, &total);
-    if (threadIdx.x == 0) part[blockIdx.x] = total;
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    return v;
 }
 
-// one block: exclusive scan of the nb block totals; total match count to *count.
-// Each thread first sums kPartsPerThread consecutive totals, so one pass of the
-// block covers 1024 x 8 of them.
-constexpr int kPartsThreads = 1024;
-constexpr int kPartsPerThread = 8;
+// Block-wide sum (any multiple of 64 threads up to 1024); `sh` holds 16 slots.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long *sh) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    v = wave_sum(v);
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    unsigned long long all = 0;
+    for (int i = 0; i < int(blockDim.x / kWave); ++i) all += sh[i];
+    __syncthreads();
+    return all;
+}
 
-__global__ __launch_bounds__(kPartsThreads) void k_scan_parts(unsigned long long *part, int64_t nb,
-                                                              int64_t *count) {
+// One block of kPartsThreads: sup[k] = exclusive prefix of the super-block
+// sums (nsup = ceil(nb / kSuper) of them); *count = the total.
+__global__ __launch_bounds__(kPartsThreads) void k_scan_parts(const unsigned long long *part, int64_t nb,
+                                                              unsigned long long *sup, int64_t *count) {
     __shared__ unsigned long long sh[kPartsThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    unsigned long long carry = 0;
-    for (int64_t base = 0; base < nb; base += int64_t(kPartsThreads) * kPartsPerThread) {
-        const int64_t i0 = base + int64_t(threadIdx.x) * kPartsPerThread;
-        unsigned long long v[kPartsPerThread], mine = 0;
+    const int64_t nsup = (nb + kSuper - 1) / kSuper;
+    // wave w sums super-blocks w, w + 16, ...: 16 coalesced loads per lane, one wave reduction
+    for (int64_t sb = w; sb < nsup; sb += kPartsThreads / kWave) {
+        unsigned long long x = 0;
 #pragma unroll
-        for (int k = 0; k < kPartsPerThread; ++k) {
-            v[k] = i0 + k < nb ? part[i0 + k] : 0ull;
-            mine += v[k];
+        for (int k = 0; k < kSuper / kWave; ++k) {
+            const int64_t i = sb * kSuper + k * kWave + lane;
+            x += i < nb ? part[i] : 0ull;
         }
-        const unsigned long long inc = wave_inclusive_scan(mine);
-        if (lane == kWave - 1) sh[w] = inc;
-        __syncthreads();
-        unsigned long long before = 0, tot = 0;
-        for (int k = 0; k < kPartsThreads / kWave; ++k) {
-            if (k < w) before += sh[k];
-            tot += sh[k];
-        }
-        __syncthreads();
-        unsigned long long run = carry + before + inc - mine;
-#pragma unroll
-        for (int k = 0; k < kPartsPerThread; ++k) {
-            if (i0 + k < nb) part[i0 + k] = run;
-            run += v[k];
-        }
-        carry += tot;
+        x = wave_sum(x);
+        if (lane == 0) sup[sb] = x;
     }
-    if (threadIdx.x == 0) *count = int64_t(carry);
+    __syncthreads();
+    // exclusive scan of the nsup sums: each thread a run of consecutive ones
+    // (the writes above are visible to the block after the barrier)
+    const int64_t per = (nsup + kPartsThreads - 1) / kPartsThreads;
+    const int64_t i0 = int64_t(threadIdx.x) * per, i1 = i0 + per < nsup ? i0 + per : nsup;
+    unsigned long long mine = 0;
+    for (int64_t i = i0; i < i1; ++i) mine += sup[i];
+    unsigned long long total;
+    unsigned long long run = block_exclusive_scan(mine, sh, &total);
+    for (int64_t i = i0; i < i1; ++i) {
+        const unsigned long long x = sup[i];
+        sup[i] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0) *count = int64_t(total);
 }
 
-// off[g] = output offset of walk g: the block's counts are staged in LDS,
-// each thread scans 4 consecutive walks, and the offsets leave through LDS.
-__global__ __launch_bounds__(kScanThreads) void k_walk_offsets(const uint32_t *cnt, int64_t nw,
-                                                               const unsigned long long *part, int64_t *off) {
-    __shared__ unsigned long long sh[kScanThreads / kWave];
-    __shared__ uint32_t c_sh[kScanBlock];
-    __shared__ int64_t o_sh[kScanBlock];
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
-#pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int k = i * kScanThreads + threadIdx.x;
-        c_sh[k] = base + k < nw ? cnt[base + k] : 0u;
-    }
-    __syncthreads();
-    unsigned long long v = 0;
-#pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) v += c_sh[threadIdx.x * kScanPerThread + i];
-    unsigned long long total;
-    unsigned long long run = part[blockIdx.x] + block_exclusive_scan(v, sh, &total);
-#pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int k = threadIdx.x * kScanPerThread + i;
-        o_sh[k] = int64_t(run);
-        run += c_sh[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) {
-        const int k = i * kScanThreads + threadIdx.x;
-        if (base + k < nw) off[base + k] = o_sh[k];
-    }
-}
+// One block of kPlaceThreads per `per_block` consecutive counting workgroups
+// (at most kPlaceWalks walks), kPlacePerThread consecutive walks per thread,
+// so that each thread's loads are all issued before the block first waits.
+// The block's first output slot is its super-block's prefix plus the totals
+// of the workgroups before it in that super-block.  A single scan then
+// carries two sums packed in 64 bits: the matches before each thread's walks
+// (high half: at most 2048 walks x (65536 + 255)) and the buffered matches
+// before them (low half: at most 2048 x kBuffered).  Every counting workgroup
+// gets a flag: nonzero when one of its walks has more matches than its buffer
+// holds.
+constexpr int kPlaceThreads = 256;
+constexpr int kPlacePerThread = 8;
+constexpr int kPlaceWalks = kPlaceThreads * kPlacePerThread;
 
-// Positions of the walks with 1..kBuffered matches, from the counting pass's
-// buffer: start = walk start + buffered start offset.  One block per 256 walks
-// enumerates the block's buffered matches in order (a scan of the buffered
-// counts in LDS) so that consecutive threads write consecutive positions;
-// the slots of walks with more matches are left to the positions pass.
-__global__ __launch_bounds__(kScanThreads) void k_scatter_buffered(const uint32_t *walk_count, const uint16_t *walk_buf,
-                                                                   const int64_t *walk_off, int64_t nwalks, int64_t S,
-                                                                   int32_t m, int64_t *positions, int64_t cap) {
-    __shared__ unsigned long long sh[kScanThreads / kWave];
-    __shared__ uint32_t first[kScanThreads + 1];  // buffered matches before each walk of the block
-    __shared__ int64_t out[kScanThreads];         // output offset of each walk
-    const int64_t g0 = int64_t(blockIdx.x) * kScanThreads;
-    const int64_t g = g0 + threadIdx.x;
-    uint32_t c = 0;
-    int64_t o = 0;
-    if (g < nwalks) {
-        c = walk_count[g];
-        o = walk_off[g];
+__global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_count, const uint16_t *walk_buf,
+                                                         const unsigned long long *part,
+                                                         const unsigned long long *sup, int64_t nwalks, int64_t nb,
+                                                         int group_walks, int per_block, int64_t S,
+                                                         int64_t *walk_off, uint32_t *wg_flag, int64_t *positions,
+                                                         int64_t cap) {
+    __shared__ unsigned long long sh[kPlaceThreads / kWave];
+    __shared__ uint32_t first[kPlaceWalks];  // buffered matches before each walk of the block
+    __shared__ int64_t out[kPlaceWalks];     // output offset of each walk
+    __shared__ uint32_t over[kPlaceWalks / kWave];  // per workgroup of the block: a walk past its buffer
+    const int t = threadIdx.x;
+    const int64_t wg0 = int64_t(blockIdx.x) * per_block;
+    const int64_t g0 = wg0 * group_walks;
+    const int bw = per_block * group_walks;  // walks of the block (a multiple of 64)
+    // loads first: this thread's walk counts, the totals before wg0 in its super-block
+    uint32_t c[kPlacePerThread];
+    const int64_t gt = g0 + t * kPlacePerThread;
+    if (t * kPlacePerThread < bw && gt + kPlacePerThread <= nwalks) {
+        // 32 aligned bytes (g0 is a multiple of 64 walks)
+        const uint4 lo = *reinterpret_cast<const uint4 *>(walk_count + gt);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(walk_count + gt + 4);
+        c[0] = lo.x; c[1] = lo.y; c[2] = lo.z; c[3] = lo.w;
+        c[4] = hi.x; c[5] = hi.y; c[6] = hi.z; c[7] = hi.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPlacePerThread; ++k) {
+            const int idx = t * kPlacePerThread + k;
+            c[k] = (idx < bw && g0 + idx < nwalks) ? walk_count[g0 + idx] : 0u;
+        }
     }
-    const uint32_t b = c <= uint32_t(kBuffered) ? c : 0u;
+    const int64_t sb = wg0 / kSuper * kSuper;
+    unsigned long long before = 0;
+    for (int64_t i = sb + t; i < wg0; i += kPlaceThreads) before += part[i];
+    const unsigned long long sup0 = sup[wg0 / kSuper];
+    if (t < per_block) over[t] = 0u;
+    const int64_t base = int64_t(sup0 + block_sum(before, sh));
+
+    uint32_t tc = 0, tb = 0;
+#pragma unroll
+    for (int k = 0; k < kPlacePerThread; ++k) {
+        tc += c[k];
+        tb += c[k] <= uint32_t(kBuffered) ? c[k] : 0u;
+    }
     unsigned long long total;
-    first[threadIdx.x] = uint32_t(block_exclusive_scan(b, sh, &total));
-    out[threadIdx.x] = o;
-    if (threadIdx.x == 0) first[kScanThreads] = uint32_t(total);
+    const unsigned long long ex = block_exclusive_scan((uint64_t(tc) << 32) | tb, sh, &total);
+    int64_t run = base + int64_t(ex >> 32);
+    uint32_t runb = uint32_t(ex);
+    const uint32_t nbuf = uint32_t(total);
+#pragma unroll
+    for (int k = 0; k < kPlacePerThread; ++k) {
+        const int idx = t * kPlacePerThread + k;
+        if (idx < bw) {
+            if (nbuf) {  // the walk table is only read when there are buffered matches
+                first[idx] = runb;
+                out[idx] = run;
+            }
+            if (c[k] > uint32_t(kBuffered)) {
+                walk_off[g0 + idx] = run;
+                over[idx / group_walks] = 1u;  // every writer stores the same value
+            }
+        }
+        run += c[k];
+        runb += c[k] <= uint32_t(kBuffered) ? c[k] : 0u;
+    }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < uint32_t(total); k += kScanThreads) {
+    if (t < per_block && wg0 + t < nb) wg_flag[wg0 + t] = over[t];
+    for (uint32_t k = t; k < nbuf; k += kPlaceThreads) {
         // the walk holding buffered match k: the last w with first[w] <= k
-        int lo = 0, hi = kScanThreads - 1;
+        int lo = 0, hi = bw - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
             if (first[mid] <= k) lo = mid; else hi = mid - 1;
@@ -584,9 +665,10 @@ const void *scan_fn(int mode) {
 // the (walks per lane, bytes per round) shapes compiled into the library, each
 // with the overlap prefetch depth for the pattern length
 const void *pick_scan(int K, int line, int mode, int m) {
-    const bool h1 = halo_units_for(m) == 1;
-    if (K == 1 && line == 128) return h1 ? scan_fn<1, 128, 1>(mode) : scan_fn<1, 128, 4>(mode);
-    if (K == 1 && line == 64) return h1 ? scan_fn<1, 64, 1>(mode) : scan_fn<1, 64, 4>(mode);
+    const int h = halo_units_for(m);
+    if (K == 1 && line == 128) return h == 1 ? scan_fn<1, 128, 1>(mode) : scan_fn<1, 128, 4>(mode);
+    if (K == 1 && line == 64)
+        return h == 1 ? scan_fn<1, 64, 1>(mode) : h == 2 ? scan_fn<1, 64, 2>(mode) : scan_fn<1, 64, 4>(mode);
     if (K == 2 && line == 64) return scan_fn<2, 64, 4>(mode);
     return nullptr;
 }
@@ -660,19 +742,23 @@ bool check_tune(const dfa_tune *t) {
 // the workspace without a device query.
 int64_t max_walks(int64_t n, const dfa_tune *t) { return n > 0 ? dfa::ceil_div(n, min_span(t)) : 0; }
 
-// workspace layout: walk counts u32[nw] | walk offsets i64[nw] | block
-// partials u64[nb] | buffered match ends u16[nw * kBuffered]
+// workspace layout: walk counts u32[nw] | walk offsets i64[nw] | workgroup
+// totals u64[nb] | super-block prefixes u64[nb / kSuper] | workgroup flags
+// u32[nb] | buffered match starts u16[nw * kBuffered], with nb sized for the
+// smallest workgroup (64 walks)
 struct WsLayout {
-    int64_t cnt = 0, off = 0, part = 0, buf = 0, total = 0;
+    int64_t cnt = 0, off = 0, part = 0, sup = 0, flag = 0, buf = 0, total = 0;
 };
 WsLayout ws_layout(int64_t nw) {
     WsLayout L;
     if (nw <= 0) return L;
-    const int64_t nb = dfa::ceil_div(nw, kScanBlock);
+    const int64_t nb = dfa::ceil_div(nw, kWave);
     L.cnt = 0;
     L.off = L.cnt + dfa::round_up(nw * 4, 256);
     L.part = L.off + dfa::round_up(nw * 8, 256);
-    L.buf = L.part + dfa::round_up(nb * 8, 256);
+    L.sup = L.part + dfa::round_up(nb * 8, 256);
+    L.flag = L.sup + dfa::round_up(dfa::ceil_div(nb, kSuper) * 8, 256);
+    L.buf = L.flag + dfa::round_up(nb * 4, 256);
     L.total = L.buf + dfa::round_up(nw * 2 * kBuffered, 256);
     return L;
 }
@@ -692,26 +778,26 @@ int kernel_vgprs(const void *fn) {
     return regs;
 }
 
-// Default waves per workgroup: the smaller of 4 and 8 whose workgroups keep
-// at least 90% of the waves a CU can hold by registers resident, given the
-// LDS each one needs (its transpose buffers plus its own copy of the table).
-// Smaller workgroups refill a CU at a finer grain; larger ones share one table
-// among more waves, which matters once the table is large (long patterns).
+// Default waves per workgroup: of 4 and 8, the one that keeps more waves
+// resident on a CU (4 on a tie), given the registers per wave and the LDS
+// each workgroup needs (its transpose buffers plus its own copy of the
+// table).  Smaller workgroups refill a CU at a finer grain; larger ones share
+// one table among more waves, which matters once the table is large (long
+// patterns).  Workgroups of 5 to 7 waves measure slower than both even where
+// they fit more waves (the text a workgroup walks is then not a power-of-two
+// number of bytes long).
 int default_wpg(const void *fn, int K, int line, int m) {
     const int regs = kernel_vgprs(fn);
     if (regs <= 0) return kDefaultWpg;
     const int per_simd = std::min(kMaxWavesPerSimd, kVgprsPerLane / int(dfa::round_up(regs, 8)));
     const int by_regs = kSimdsPerCu * std::max(1, per_simd);
-    int waves[2], best = 0;
     const int cand[2] = {4, 8};
+    int waves[2];
     for (int i = 0; i < 2; ++i) {
         const int groups = int(kLdsPerCu / scan_lds_bytes(cand[i], K, line, m));
         waves[i] = std::min(by_regs, groups * cand[i]);
-        best = std::max(best, waves[i]);
     }
-    for (int i = 0; i < 2; ++i)
-        if (10 * waves[i] >= 9 * best) return cand[i];
-    return kDefaultWpg;
+    return waves[1] > waves[0] ? cand[1] : cand[0];
 }
 
 bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
@@ -759,7 +845,29 @@ int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) 
     return DFA_OK;
 }
 
+// dfa_set_scan_events: events bracketing the text walk of this thread's calls
+thread_local hipEvent_t t_scan_begin = nullptr, t_scan_end = nullptr;
+
+// The walk over the whole text, bracketed by the measurement events if set.
+int launch_walk(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) {
+    if (t_scan_begin && !hip_ok(hipEventRecord(t_scan_begin, st), "hipEventRecord")) return DFA_EHIP;
+    const int rc = launch_scan(pl, mode, sp, st);
+    if (rc == DFA_OK && t_scan_end && !hip_ok(hipEventRecord(t_scan_end, st), "hipEventRecord")) return DFA_EHIP;
+    return rc;
+}
+
 }  // namespace
+
+extern "C" int dfa_set_scan_events(void *begin, void *end) {
+    if ((begin == nullptr) != (end == nullptr)) {
+        dfa::set_error("dfa_set_scan_events: give both events or neither");
+        return DFA_EINVAL;
+    }
+    t_scan_begin = reinterpret_cast<hipEvent_t>(begin);
+    t_scan_end = reinterpret_cast<hipEvent_t>(end);
+    dfa::clear_error();
+    return DFA_OK;
+}
 
 extern "C" int64_t dfa_count_workspace_bytes(int64_t n, int32_t m, int32_t want_positions,
                                              const dfa_tune *tune) {
@@ -805,8 +913,11 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
         }
     }
 
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(count));
-    if (!hip_ok(hipGetLastError(), "k_zero_u64 launch")) return DFA_EHIP;
+    if (n == 0 || !want_pos) {
+        // the count-only scan adds into *count; the positions path writes it
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(count));
+        if (!hip_ok(hipGetLastError(), "k_zero_u64 launch")) return DFA_EHIP;
+    }
     if (n == 0) {
         dfa::clear_error();
         return DFA_OK;
@@ -831,32 +942,39 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     sp.cap = cap;
 
     if (!want_pos) {
-        int rc = launch_scan(pl, kCount, sp, st);
+        int rc = launch_walk(pl, kCount, sp, st);
         if (rc == DFA_OK) dfa::clear_error();
         return rc;
     }
 
     uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
     const int64_t nw = pl.nwalks;
-    const int64_t nb = dfa::ceil_div(nw, kScanBlock);
+    const int group_walks = pl.wpg * kWave * pl.K;  // walks of one workgroup of both passes
     const WsLayout L = ws_layout(nw);
     uint32_t *wcnt = reinterpret_cast<uint32_t *>(ws + L.cnt);
     int64_t *woff = reinterpret_cast<int64_t *>(ws + L.off);
     unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + L.part);
+    unsigned long long *sup = reinterpret_cast<unsigned long long *>(ws + L.sup);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(ws + L.flag);
     uint16_t *wbuf = reinterpret_cast<uint16_t *>(ws + L.buf);
+    if (group_walks > kMaxGroupWalks || pl.blocks > dfa::ceil_div(nw, kWave)) {
+        dfa::set_error("dfa_count: %d walks per workgroup (at most %d)", group_walks, kMaxGroupWalks);
+        return DFA_EINVAL;
+    }
 
     sp.walk_count = wcnt;
     sp.walk_buf = wbuf;
-    int rc = launch_scan(pl, kCountPerWalk, sp, st);
+    sp.wg_part = part;
+    int rc = launch_walk(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
-    hipLaunchKernelGGL(k_walk_sums, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw, part);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, part, nb, count);
-    hipLaunchKernelGGL(k_walk_offsets, dim3(unsigned(nb)), dim3(kScanThreads), 0, st, wcnt, nw,
-                       (const unsigned long long *)part, woff);
-    hipLaunchKernelGGL(k_scatter_buffered, dim3(unsigned(dfa::ceil_div(nw, kScanThreads))), dim3(kScanThreads), 0, st,
-                       (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const int64_t *)woff, nw, pl.S, m, positions,
-                       cap);
-    if (!hip_ok(hipGetLastError(), "prefix-sum launch")) return DFA_EHIP;
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part, pl.blocks,
+                       sup, count);
+    const int per_block = kPlaceWalks / group_walks;  // counting workgroups per placement block
+    hipLaunchKernelGGL(k_place, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0, st, (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const unsigned long long *)part,
+                       (const unsigned long long *)sup, nw, pl.blocks, group_walks, per_block, pl.S, woff, flag,
+                       positions, cap);
+    if (!hip_ok(hipGetLastError(), "placement launch")) return DFA_EHIP;
+    sp.wg_flag = flag;
     sp.walk_off = woff;
     sp.positions = positions;
     rc = launch_scan(pl, kPositions, sp, st);

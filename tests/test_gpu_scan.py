@@ -59,7 +59,7 @@ def test_tiny_uniform_workload():
     assert w.offsets[0] in pos.tolist()
 
 
-@pytest.mark.parametrize("m", [1, 2, 4, 8, 17, 64, 255])
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 17, 18, 33, 34, 64, 255])
 def test_ragged_sizes(m):
     rng = np.random.default_rng(m)
     pat = synth.random_pattern(m, rng)
@@ -102,6 +102,25 @@ def test_periodic_texts_dense_matches():
     text = np.frombuffer(b"AC" * k, np.uint8).copy()
     c, pos = gpu_result(api.to_device(text), b"ACA")
     assert c == k - 1 and np.array_equal(pos, np.arange(0, 2 * k - 3, 2))
+
+
+def test_match_bursts_between_sparse_stretches():
+    """Matches packed together (every lane of a wave matching in the same bytes) between
+    long stretches without any, so that the per-walk counting pass changes how it walks
+    many times within one walk and one wave."""
+    rng = np.random.default_rng(11)
+    n = (1 << 21) + 45
+    text = synth.genome_like(n, 12, 0.0, 300)
+    for m in (2, 5, 12, 20, 40):
+        pat = synth.random_pattern(m, rng)
+        t = text.copy()
+        starts = rng.integers(0, n - 4096, size=60)
+        for s0 in starts:  # a burst: the pattern repeated back to back
+            reps = int(rng.integers(1, 4096 // m))
+            burst = np.frombuffer(pat * reps, np.uint8)
+            t[s0:s0 + burst.size] = burst
+        say(f"bursts m={m}")
+        check(t, pat)
 
 
 def test_all_byte_values():

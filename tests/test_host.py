@@ -219,3 +219,12 @@ def test_one_hip_runtime_whatever_the_import_order():
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_scan_events_hook_arguments():
+    """dfa_set_scan_events takes both events or neither (no GPU call is made)."""
+    assert api.lib.dfa_set_scan_events(None, None) == api.DFA_OK
+    assert api.lib.dfa_set_scan_events(ctypes.c_void_p(16), None) == api.DFA_EINVAL
+    assert "both events" in api.last_error()
+    assert api.lib.dfa_set_scan_events(None, ctypes.c_void_p(16)) == api.DFA_EINVAL
+    assert api.lib.dfa_set_scan_events(None, None) == api.DFA_OK
