@@ -60,9 +60,15 @@ struct ScanParams {
     int64_t S;         // span bytes per walk (multiple of 16)
     int64_t nwalks;
     unsigned long long *total;    // kCount: += matches
-    uint32_t *walk_count;         // kCountPerWalk: matches per walk (read back by kPositions)
-    uint16_t *walk_buf;           // kCountPerWalk: start offsets (within the walk) of its first kBuffered matches
+    uint32_t *walk_count;         // kCountPerWalk: matches per walk, written by waves with a match
+                                  // (read back by kPositions)
+    uint16_t *walk_buf;           // kCountPerWalk: start offsets (within the walk) of its first kStaged matches
+    uint16_t *walk_buf1;          //   and of the next kBuffered - kStaged
     unsigned long long *wg_part;  // kCountPerWalk: matches per workgroup
+    uint32_t *wg_waves;           // kCountPerWalk: bit w set when wave w of the workgroup had a match
+                                  // (read back by kPositions)
+    int32_t stage;                // kCountPerWalk: stage records in LDS (plans for short patterns)
+    uint32_t rec_lds;             // in the kernel: LDS address of the wave's staged records (or 0)
     const uint32_t *wg_flag;      // kPositions: nonzero for a workgroup with a walk past its buffer
     const int64_t *walk_off;      // kPositions: output offset per walk (walks past their buffer only)
     int64_t *positions;         // kPositions
@@ -71,9 +77,25 @@ struct ScanParams {
     int64_t wg_cap;                // workgroups with room in wg_times
 };
 
-// matches per walk whose end offsets the counting pass keeps (in the
-// workspace); walks with more are walked again by the positions pass
+// matches per walk whose start offsets the counting pass keeps (in the
+// workspace); walks with more are walked again by the positions pass.  The
+// first kStaged of them and the rest live in two arrays of kStaged entries
+// per walk, so that the first halves of consecutive walks are contiguous.
 constexpr int kBuffered = 16;
+constexpr int kStaged = 8;
+// Short patterns, one walk per lane: the per-walk counting pass keeps each
+// walk's first kStaged records in LDS ([record][lane] 16-bit, 1 KiB per wave)
+// and stores them in one 16-byte store per lane at the end of the walk.
+// Records stored to HBM as they are found land in lines that leave L2 before
+// the walk is done, and every such partial line costs a write of its own; the
+// staging costs LDS, i.e. resident waves.  It pays where matches are dense:
+// on a 4-letter text a pattern of m <= 6 bytes is expected about once per
+// 4^m <= 4096 bytes, several times per walk; longer ones mostly not at all.
+constexpr int kRecBytes = kStaged * kWave * 2;
+constexpr int kStageMaxM = 6;
+__host__ __device__ constexpr bool stages_records(int K, int MODE, int H) {
+    return MODE == kCountPerWalk && K == 1 && H == 1;
+}
 // buffered matches are kept as 16-bit start offsets within the walk (a walk
 // owns the starts of its span): the positions path needs S <= 65536
 constexpr int64_t kMaxPositionsSpan = 65536;
@@ -87,20 +109,31 @@ struct WalkLane {
     int64_t off;     // next output slot (positions pass)
 };
 
-// The buffer of walk s of this lane: p.walk_buf points at the wave's first
-// walk in the per-walk counting pass, so the lane's own part of it follows
-// from the lane index alone (no pointer held per lane).
-__device__ __forceinline__ uint16_t *walk_slots(const ScanParams &p, int s) {
-    return p.walk_buf + (s * kWave + int(__lane_id())) * kBuffered;
+typedef __attribute__((address_space(3))) uint16_t lds_u16w;
+
+// Record `idx` (< kBuffered) of walk s of this lane.  p.walk_buf and
+// p.walk_buf1 point at the wave's first walk in the per-walk counting pass,
+// so the lane's own entries follow from the lane index alone (no pointer
+// held per lane); p.rec_lds is nonzero when the first kStaged wait in LDS.
+__device__ __forceinline__ void put_record(const ScanParams &p, int s, uint32_t idx, uint16_t v) {
+    const uint32_t w = uint32_t(s * kWave) + __lane_id();
+    if (idx < uint32_t(kStaged)) {
+        if (p.rec_lds)
+            *reinterpret_cast<lds_u16w *>(uintptr_t(p.rec_lds + 2u * (idx * kWave + __lane_id()))) = v;
+        else
+            p.walk_buf[w * kStaged + idx] = v;
+    } else {
+        p.walk_buf1[w * kStaged + idx - kStaged] = v;
+    }
 }
 
 // The start offsets of a lane's matches in one unit (hit mask from
 // walk16_hits, first byte in bit 15; a match ending at byte j starts at
 // j - (m - 1)), in increasing order, into the walk's buffer.
-__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, uint16_t *buf) {
+__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, const ScanParams &p) {
     while (hm) {
         const int b = 31 - __clz(hm);
-        if (w.cnt < uint32_t(kBuffered)) buf[w.cnt] = uint16_t(jb + uint32_t(15 - b) - (m - 1));
+        if (w.cnt < uint32_t(kBuffered)) put_record(p, 0, w.cnt, uint16_t(jb + uint32_t(15 - b) - (m - 1)));
         ++w.cnt;
         hm ^= 1u << b;
     }
@@ -130,7 +163,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
         if (__builtin_amdgcn_readfirstlane(acc)) {
             walk16_hits(q[0], t[0], hm, m);
             const bool any = __ballot(hm != 0) != 0;
-            if (any) record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+            if (any) record_hits(hm, jb, m, wl[0], p);
             acc = any ? 1u : 0u;
         } else {
             const uint32_t q0 = q[0];
@@ -139,7 +172,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
             if (__builtin_amdgcn_readfirstlane(a)) {
                 q[0] = q0;
                 walk16_hits(q[0], t[0], hm, m);
-                record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+                record_hits(hm, jb, m, wl[0], p);
                 acc = 1u;
             }
         }
@@ -160,7 +193,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
                     add_hits(acc, hit);
                 } else if (MODE == kCountPerWalk) {
                     if (hit) {
-                        if (wl[s].cnt < uint32_t(kBuffered)) walk_slots(p, s)[wl[s].cnt] = uint16_t(j - (m - 1));
+                        if (wl[s].cnt < uint32_t(kBuffered)) put_record(p, s, wl[s].cnt, uint16_t(j - (m - 1)));
                         ++wl[s].cnt;
                     }
                 } else if (hit) {
@@ -189,7 +222,7 @@ __device__ __forceinline__ void walk_overlap_unit(const v4u (&t)[K], uint32_t (&
         if (MODE == kCount)
             extra += uint32_t(__popc(hm));
         else if (__ballot(hm != 0))
-            record_hits(hm, jb, m, wl[0], walk_slots(p, 0));
+            record_hits(hm, jb, m, wl[0], p);
     } else {
         walk_unit<K, MODE, true>(t, q, m, jb, acc, wl, p);
     }
@@ -267,7 +300,13 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     __syncthreads();
 
     const int64_t g0 = (int64_t(blockIdx.x) * nwaves + wave) * (kWave * K);
-    if (MODE == kCountPerWalk) p.walk_buf += g0 * kBuffered;
+    if (MODE == kCountPerWalk) {
+        p.walk_buf += g0 * kStaged;
+        p.walk_buf1 += g0 * kStaged;
+        p.rec_lds = stages_records(K, MODE, H) && p.stage
+                        ? uint32_t(table_lds_bytes(p.m) + nwaves * (K * kWave * LINE) + wave * kRecBytes)
+                        : 0u;
+    }
     const uint32_t m = uint32_t(p.m);
     const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(p.S) + 16u * uint32_t(lane % G::U);
 
@@ -293,7 +332,8 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
             // only walks whose matches did not all fit the counting pass's buffer
             // (the other lanes walk along without writing: their offset is past
             // any capacity)
-            const bool has = g < p.nwalks && p.walk_count[g] > uint32_t(kBuffered);
+            const bool has = g < p.nwalks && ((p.wg_waves[blockIdx.x] >> wave) & 1u) &&
+                             p.walk_count[g] > uint32_t(kBuffered);
             wl[s].off = has ? p.walk_off[g] : (int64_t(1) << 62);
             any_work |= has;
         }
@@ -408,10 +448,27 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     if (MODE == kCountPerWalk) {
         uint32_t c = 0;
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int64_t g = g0 + s * kWave + lane;
-            if (g < p.nwalks) p.walk_count[g] = wl[s].cnt;
-            c += wl[s].cnt;
+        for (int s = 0; s < K; ++s) c += wl[s].cnt;
+        // only a wave with a match writes its walks' counts (and its staged
+        // records); the workgroup's wave mask says which did
+        if (__ballot(c != 0)) {
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const int64_t g = g0 + s * kWave + lane;
+                if (g < p.nwalks) p.walk_count[g] = wl[s].cnt;
+            }
+            if (stages_records(K, MODE, H) && p.rec_lds && g0 + lane < p.nwalks) {
+                // entries past the walk's count are stale and never read
+                uint32_t r[kStaged / 2];
+#pragma unroll
+                for (int k = 0; k < kStaged / 2; ++k) {
+                    const uint32_t a = p.rec_lds + 2u * (uint32_t(2 * k) * kWave + uint32_t(lane));
+                    const uint32_t lo = *reinterpret_cast<const lds_u16w *>(uintptr_t(a));
+                    const uint32_t hi = *reinterpret_cast<const lds_u16w *>(uintptr_t(a + 2u * kWave));
+                    r[k] = lo | (hi << 16);
+                }
+                *reinterpret_cast<uint4 *>(p.walk_buf + lane * kStaged) = make_uint4(r[0], r[1], r[2], r[3]);
+            }
         }
         // the wave's matches, summed over its lanes
 #pragma unroll
@@ -427,10 +484,14 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     if (threadIdx.x == 0) {
         unsigned long long sum = 0;
         for (int w = 0; w < nwaves; ++w) sum += red[w];
-        if (MODE == kCountPerWalk)
+        if (MODE == kCountPerWalk) {
             p.wg_part[blockIdx.x] = sum;
-        else if (sum)
+            uint32_t mask = 0;
+            for (int w = 0; w < nwaves; ++w) mask |= red[w] ? 1u << w : 0u;
+            p.wg_waves[blockIdx.x] = mask;
+        } else if (sum) {
             atomicAdd(p.total, sum);
+        }
         if (timed) {
             unsigned long long *t = p.wg_times + 3 * int64_t(blockIdx.x);
             t[0] = t_wall;
@@ -553,17 +614,20 @@ __global__ __launch_bounds__(kPartsThreads) void k_scan_parts(const unsigned lon
 // of the workgroups before it in that super-block.  A single scan then
 // carries two sums packed in 64 bits: the matches before each thread's walks
 // (high half: at most 2048 walks x (65536 + 255)) and the buffered matches
-// before them (low half: at most 2048 x kBuffered).  Every counting workgroup
-// gets a flag: nonzero when one of its walks has more matches than its buffer
-// holds.
+// before them (low half: at most 2048 x kBuffered).  A walk's count is read
+// only when its wave had a match (the wave mask of its workgroup); the other
+// counts are zero and their memory may hold an earlier call's.  Every
+// counting workgroup gets a flag: nonzero when one of its walks has more
+// matches than its buffer holds.
 constexpr int kPlaceThreads = 256;
 constexpr int kPlacePerThread = 8;
 constexpr int kPlaceWalks = kPlaceThreads * kPlacePerThread;
 
 __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_count, const uint16_t *walk_buf,
+                                                         const uint16_t *walk_buf1, const uint32_t *wg_waves,
                                                          const unsigned long long *part,
                                                          const unsigned long long *sup, int64_t nwalks, int64_t nb,
-                                                         int group_walks, int per_block, int64_t S,
+                                                         int group_walks, int wave_walks, int per_block, int64_t S,
                                                          int64_t *walk_off, uint32_t *wg_flag, int64_t *positions,
                                                          int64_t cap) {
     __shared__ unsigned long long sh[kPlaceThreads / kWave];
@@ -577,7 +641,14 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
     // loads first: this thread's walk counts, the totals before wg0 in its super-block
     uint32_t c[kPlacePerThread];
     const int64_t gt = g0 + t * kPlacePerThread;
-    if (t * kPlacePerThread < bw && gt + kPlacePerThread <= nwalks) {
+    // the thread's walks lie in one wave (wave_walks is a multiple of 64)
+    const int lw = t * kPlacePerThread / group_walks;
+    const bool wrote = t * kPlacePerThread < bw && wg0 + lw < nb &&
+                       ((wg_waves[wg0 + lw] >> (t * kPlacePerThread % group_walks / wave_walks)) & 1u);
+    if (!wrote) {
+#pragma unroll
+        for (int k = 0; k < kPlacePerThread; ++k) c[k] = 0u;
+    } else if (gt + kPlacePerThread <= nwalks) {
         // 32 aligned bytes (g0 is a multiple of 64 walks)
         const uint4 lo = *reinterpret_cast<const uint4 *>(walk_count + gt);
         const uint4 hi = *reinterpret_cast<const uint4 *>(walk_count + gt + 4);
@@ -636,7 +707,9 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
         const uint32_t i = k - first[lo];
         const int64_t dst = out[lo] + i;
         const int64_t gw = g0 + lo;
-        if (dst < cap) positions[dst] = gw * S + int64_t(walk_buf[gw * kBuffered + i]);
+        if (dst < cap)
+            positions[dst] = gw * S + int64_t(i < uint32_t(kStaged) ? walk_buf[gw * kStaged + i]
+                                                                     : walk_buf1[gw * kStaged + i - kStaged]);
     }
 }
 
@@ -673,8 +746,14 @@ const void *pick_scan(int K, int line, int mode, int m) {
     return nullptr;
 }
 
-size_t scan_lds_bytes(int wpg, int K, int line, int m) {
-    return size_t(wpg) * K * kWave * line + size_t(table_lds_bytes(m));
+// LDS of one workgroup of a plan made for `mode`: the table, one transpose
+// buffer per wave and, where the per-walk counting pass stages its records,
+// 1 KiB more per wave (the positions pass runs with the same plan and size).
+bool plan_stages(int K, int m, int mode) { return stages_records(K, mode, halo_units_for(m)) && m <= kStageMaxM; }
+
+size_t scan_lds_bytes(int wpg, int K, int line, int m, int mode) {
+    const bool rec = plan_stages(K, m, mode);
+    return size_t(wpg) * (K * kWave * line + (rec ? kRecBytes : 0)) + size_t(table_lds_bytes(m));
 }
 
 // Default span of one walk: 8 m rounded up to whole lines, at least 512 and
@@ -744,10 +823,11 @@ int64_t max_walks(int64_t n, const dfa_tune *t) { return n > 0 ? dfa::ceil_div(n
 
 // workspace layout: walk counts u32[nw] | walk offsets i64[nw] | workgroup
 // totals u64[nb] | super-block prefixes u64[nb / kSuper] | workgroup flags
-// u32[nb] | buffered match starts u16[nw * kBuffered], with nb sized for the
+// u32[nb] | workgroup wave masks u32[nb] | first kStaged match starts
+// u16[nw * kStaged] | the next ones u16[nw * kStaged], with nb sized for the
 // smallest workgroup (64 walks)
 struct WsLayout {
-    int64_t cnt = 0, off = 0, part = 0, sup = 0, flag = 0, buf = 0, total = 0;
+    int64_t cnt = 0, off = 0, part = 0, sup = 0, flag = 0, waves = 0, buf = 0, buf1 = 0, total = 0;
 };
 WsLayout ws_layout(int64_t nw) {
     WsLayout L;
@@ -758,8 +838,10 @@ WsLayout ws_layout(int64_t nw) {
     L.part = L.off + dfa::round_up(nw * 8, 256);
     L.sup = L.part + dfa::round_up(nb * 8, 256);
     L.flag = L.sup + dfa::round_up(dfa::ceil_div(nb, kSuper) * 8, 256);
-    L.buf = L.flag + dfa::round_up(nb * 4, 256);
-    L.total = L.buf + dfa::round_up(nw * 2 * kBuffered, 256);
+    L.waves = L.flag + dfa::round_up(nb * 4, 256);
+    L.buf = L.waves + dfa::round_up(nb * 4, 256);
+    L.buf1 = L.buf + dfa::round_up(nw * 2 * kStaged, 256);
+    L.total = L.buf1 + dfa::round_up(nw * 2 * (kBuffered - kStaged), 256);
     return L;
 }
 int64_t workspace_for(int64_t nw) { return ws_layout(nw).total; }
@@ -786,7 +868,7 @@ int kernel_vgprs(const void *fn) {
 // patterns).  Workgroups of 5 to 7 waves measure slower than both even where
 // they fit more waves (the text a workgroup walks is then not a power-of-two
 // number of bytes long).
-int default_wpg(const void *fn, int K, int line, int m) {
+int default_wpg(const void *fn, int K, int line, int m, int mode) {
     const int regs = kernel_vgprs(fn);
     if (regs <= 0) return kDefaultWpg;
     const int per_simd = std::min(kMaxWavesPerSimd, kVgprsPerLane / int(dfa::round_up(regs, 8)));
@@ -794,7 +876,7 @@ int default_wpg(const void *fn, int K, int line, int m) {
     const int cand[2] = {4, 8};
     int waves[2];
     for (int i = 0; i < 2; ++i) {
-        const int groups = int(kLdsPerCu / scan_lds_bytes(cand[i], K, line, m));
+        const int groups = int(kLdsPerCu / scan_lds_bytes(cand[i], K, line, m, mode));
         waves[i] = std::min(by_regs, groups * cand[i]);
     }
     return waves[1] > waves[0] ? cand[1] : cand[0];
@@ -807,9 +889,9 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
         pl.wpg = t->waves_per_group;
     } else {
         const void *fn = pick_scan(pl.K, pl.line, mode, m);
-        pl.wpg = fn ? default_wpg(fn, pl.K, pl.line, m) : kDefaultWpg;
+        pl.wpg = fn ? default_wpg(fn, pl.K, pl.line, m, mode) : kDefaultWpg;
     }
-    pl.lds = scan_lds_bytes(pl.wpg, pl.K, pl.line, m);
+    pl.lds = scan_lds_bytes(pl.wpg, pl.K, pl.line, m, mode);
     if (t && t->chain_bytes > 0) {
         pl.S = t->chain_bytes;
     } else {
@@ -837,7 +919,7 @@ int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) 
         return DFA_EINVAL;
     }
     // allow the largest table (m = 255) with the largest workgroup
-    if (!dfa::allow_lds(fn, int(scan_lds_bytes(8, 1, 128, DFA_MAX_M)))) return DFA_EHIP;
+    if (!dfa::allow_lds(fn, int(scan_lds_bytes(8, 1, 128, DFA_MAX_M, kCount)))) return DFA_EHIP;
     void *args[] = {const_cast<ScanParams *>(&sp)};
     if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(pl.blocks)), dim3(pl.wpg * kWave), args, pl.lds, st),
                 "k_scan launch"))
@@ -956,23 +1038,29 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + L.part);
     unsigned long long *sup = reinterpret_cast<unsigned long long *>(ws + L.sup);
     uint32_t *flag = reinterpret_cast<uint32_t *>(ws + L.flag);
+    uint32_t *waves = reinterpret_cast<uint32_t *>(ws + L.waves);
     uint16_t *wbuf = reinterpret_cast<uint16_t *>(ws + L.buf);
+    uint16_t *wbuf1 = reinterpret_cast<uint16_t *>(ws + L.buf1);
     if (group_walks > kMaxGroupWalks || pl.blocks > dfa::ceil_div(nw, kWave)) {
         dfa::set_error("dfa_count: %d walks per workgroup (at most %d)", group_walks, kMaxGroupWalks);
         return DFA_EINVAL;
     }
 
     sp.walk_count = wcnt;
+    sp.stage = plan_stages(pl.K, m, kCountPerWalk) ? 1 : 0;
     sp.walk_buf = wbuf;
+    sp.walk_buf1 = wbuf1;
     sp.wg_part = part;
+    sp.wg_waves = waves;
     int rc = launch_walk(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part, pl.blocks,
                        sup, count);
     const int per_block = kPlaceWalks / group_walks;  // counting workgroups per placement block
-    hipLaunchKernelGGL(k_place, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0, st, (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const unsigned long long *)part,
-                       (const unsigned long long *)sup, nw, pl.blocks, group_walks, per_block, pl.S, woff, flag,
-                       positions, cap);
+    hipLaunchKernelGGL(k_place, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0, st,
+                       (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const uint16_t *)wbuf1,
+                       (const uint32_t *)waves, (const unsigned long long *)part, (const unsigned long long *)sup, nw,
+                       pl.blocks, group_walks, kWave * pl.K, per_block, pl.S, woff, flag, positions, cap);
     if (!hip_ok(hipGetLastError(), "placement launch")) return DFA_EHIP;
     sp.wg_flag = flag;
     sp.walk_off = woff;
