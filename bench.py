@@ -535,7 +535,7 @@ def main(argv=None) -> int:
         "count_only_frac": round(count_only_gbs / HBM_PEAK_GBS, 4),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_scan per-walk counting pass (the text walk of count + positions)",
+            "kernel": "k_scan text walk of count + positions (per-walk counts for m <= 17, per-wave counts above)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

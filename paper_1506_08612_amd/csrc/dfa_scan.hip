@@ -49,7 +49,12 @@ namespace {
 
 using namespace dfa_dev;
 
-enum Mode { kCount = 0, kCountPerWalk = 1, kPositions = 2 };
+// kCount: one wave-wide count, one atomic per workgroup.  kCountPerWalk: a
+// count and the first kBuffered match starts per walk.  kPositions: the
+// positions of the walks past their buffer.  kCountPerWave: the count-only
+// walk, one count per wave (the positions of its waves with a match come
+// from k_rewalk).
+enum Mode { kCount = 0, kCountPerWalk = 1, kPositions = 2, kCountPerWave = 3 };
 
 struct ScanParams {
     const uint8_t *text;
@@ -151,6 +156,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
         walk16_count(q[0], t[0], acc, m);
         return;
     }
+
     if constexpr (MODE == kCountPerWalk && !GUARD && K == 1) {
         // Each wave picks per unit how to walk it.  While its last unit had no
         // match it walks like the count-only scan (one wave-wide count in a
@@ -267,7 +273,121 @@ constexpr int halo_units_for(int m) { return m <= 17 ? 1 : m <= 33 ? 2 : 4; }
 // with 4 overlap units would otherwise need 81 (the compiler then keeps one
 // overlap unit in scratch between the first round and the end of the walk).
 template <int K, int LINE, int MODE>
-constexpr int scan_waves_per_eu() { return (K == 1 && LINE == 64 && MODE != kPositions) ? 6 : 1; }
+constexpr int scan_waves_per_eu() {
+    return (K == 1 && LINE == 64 && (MODE == kCount || MODE == kCountPerWalk || MODE == kCountPerWave)) ? 6 : 1;
+}
+
+// The walks of one wave (64 x K of them, from walk g0) over their spans and
+// overlaps: the whole-wave path when every load lies inside the text, else
+// the guarded one.  WM is the walking mode: kCount, kCountPerWalk or
+// kPositions.
+template <int K, int LINE, int WM, int H>
+__device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane, int64_t g0, uint32_t m,
+                                          uint32_t lane_off, uint32_t (&q)[K], uint32_t &acc, WalkLane (&wl)[K]) {
+    using G = Geo<LINE>;
+    // whole wave in bounds: every load of every round lies inside the text
+    const int64_t glast = g0 + kWave * K - 1;
+    const bool full = glast < p.nwalks && glast * p.S + int64_t(p.rounds) * LINE <= p.n;
+
+    if (full) {
+        // The span [0, S) streams in R rounds; the overlap [S, S + m - 1) is
+        // the start of the next span, which the neighbouring lane (the next
+        // walk) receives in round 0.  Right after round 0 is staged, each lane
+        // copies the first H units of its neighbour's row out of the wave's
+        // buffer and keeps them in registers until the end of the walk; only
+        // the wave's last walk, whose neighbour belongs to another wave,
+        // loads them from memory.  Fetching the overlap at the end of the
+        // walk instead would miss in L2 and cost a whole line of HBM per
+        // walk.  Units past H (m > 65) are loaded at the end.
+        const int R = int((p.S + LINE - 1) / LINE);
+        const int rlast = R - 1;
+        const int lastlen = int(p.S - int64_t(rlast) * LINE);  // bytes of the last round (LINE unless S is not a
+                                                               // multiple of LINE)
+        // Loads run two rounds ahead of the walk: pa holds even rounds, pb odd
+        // ones.  A short last round fetches only the units it walks: lanes past
+        // them repeat the last unit's address, a load of the same line.  A
+        // fetch past the last round reads the first line of the text instead
+        // (always cached), so that both buffers are always written and stay
+        // in registers without touching another line of HBM.  With 64-byte
+        // rounds, rounds r + 2 and r + 3 are the two halves of the walks' next
+        // 128-byte lines; both are requested back to back so that the second
+        // half finds the line still in L2 (requested one round apart, the
+        // shared line is evicted first and read twice).
+        const uint32_t ulast = uint32_t(lastlen + 15) / 16;
+        const uint32_t lane_unit = uint32_t(lane % G::U);
+        const uint32_t off_last = lane_off - 16u * lane_unit + 16u * (lane_unit < ulast ? lane_unit : ulast - 1);
+        const uint32_t off_none = 16u * lane_unit;
+        const int64_t wb = g0 * p.S;
+        v4u pa[K][G::U], pb[K][G::U];
+        fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
+        fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
+        const int hu = (p.m - 1 + 15) / 16;  // overlap units
+        v4u halo[K][H];
+        // round 0 (and 1), then the steady state from round 2
+        stage_round<K, LINE>(pa, xb, lane);
+        grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
+        if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+        walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
+        if (rlast >= 1) {
+            stage_round<K, LINE>(pb, xb, lane);
+            if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
+                                             p);
+        }
+        for (int r = 2; r < R; r += 2) {
+            stage_round<K, LINE>(pa, xb, lane);
+            if (LINE == 128)
+                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
+                                             acc, wl, p);
+            if (r + 1 > rlast) break;
+            stage_round<K, LINE>(pb, xb, lane);
+            if (LINE == 64)
+                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
+            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
+                                             r + 1 == rlast ? lastlen : LINE, acc, wl, p);
+        }
+        // the overlap, from registers, then (m > 65) the rest of it from memory
+        const uint32_t hb = uint32_t(p.S);
+        uint32_t extra = 0;
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+            if (u < hu) {
+                v4u t[K];
+#pragma unroll
+                for (int s = 0; s < K; ++s) t[s] = halo[s][u];
+                const uint32_t nv = m - 1 - 16u * u;
+                walk_overlap_unit<K, WM>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
+            }
+        }
+        for (int u = H; u < hu; ++u) {
+            v4u t[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s)
+                t[s] = *reinterpret_cast<const v4u *>(p.text + (g0 + s * kWave + lane + 1) * p.S + 16 * u);
+            const uint32_t nv = m - 1 - 16u * u;
+            walk_overlap_unit<K, WM>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
+        }
+        if (WM == kCount && K == 1) {
+            // the overlap's hits, summed over the wave
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) extra += uint32_t(__shfl_xor(int(extra), o));
+            acc = uint32_t(__builtin_amdgcn_readfirstlane(int(acc))) +
+                  uint32_t(__builtin_amdgcn_readfirstlane(int(extra)));
+        }
+    } else {
+        v4u pf[K][G::U];
+        fetch_round<K, LINE, true>(pf, p.text, p.n, g0 * p.S, p.S, lane_off, 0);
+        for (int r = 0; r < p.rounds; ++r) {
+            stage_round<K, LINE>(pf, xb, lane);
+            if (r + 1 < p.rounds) fetch_round<K, LINE, true>(pf, p.text, p.n, g0 * p.S, p.S, lane_off, r + 1);
+            walk_round<K, LINE, WM, true>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
+        }
+    }
+
+}
 
 template <int K, int LINE, int MODE, int H>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<K, LINE, MODE>())))
@@ -340,110 +460,12 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     }
     if (MODE == kPositions && __ballot(any_work) == 0) return;  // nothing left to write in this wave
 
-    // whole wave in bounds: every load of every round lies inside the text
-    const int64_t glast = g0 + kWave * K - 1;
-    const bool full = glast < p.nwalks && glast * p.S + int64_t(p.rounds) * LINE <= p.n;
     uint32_t acc = 0;
-
-    if (full) {
-        // The span [0, S) streams in R rounds; the overlap [S, S + m - 1) is
-        // the start of the next span, which the neighbouring lane (the next
-        // walk) receives in round 0.  Right after round 0 is staged, each lane
-        // copies the first H units of its neighbour's row out of the wave's
-        // buffer and keeps them in registers until the end of the walk; only
-        // the wave's last walk, whose neighbour belongs to another wave,
-        // loads them from memory.  Fetching the overlap at the end of the
-        // walk instead would miss in L2 and cost a whole line of HBM per
-        // walk.  Units past H (m > 65) are loaded at the end.
-        const int R = int((p.S + LINE - 1) / LINE);
-        const int rlast = R - 1;
-        const int lastlen = int(p.S - int64_t(rlast) * LINE);  // bytes of the last round (LINE unless S is not a
-                                                               // multiple of LINE)
-        // Loads run two rounds ahead of the walk: pa holds even rounds, pb odd
-        // ones.  A short last round fetches only the units it walks: lanes past
-        // them repeat the last unit's address, a load of the same line.  A
-        // fetch past the last round reads the first line of the text instead
-        // (always cached), so that both buffers are always written and stay
-        // in registers without touching another line of HBM.  With 64-byte
-        // rounds, rounds r + 2 and r + 3 are the two halves of the walks' next
-        // 128-byte lines; both are requested back to back so that the second
-        // half finds the line still in L2 (requested one round apart, the
-        // shared line is evicted first and read twice).
-        const uint32_t ulast = uint32_t(lastlen + 15) / 16;
-        const uint32_t lane_unit = uint32_t(lane % G::U);
-        const uint32_t off_last = lane_off - 16u * lane_unit + 16u * (lane_unit < ulast ? lane_unit : ulast - 1);
-        const uint32_t off_none = 16u * lane_unit;
-        const int64_t wb = g0 * p.S;
-        v4u pa[K][G::U], pb[K][G::U];
-        fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
-        fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
-        const int hu = (p.m - 1 + 15) / 16;  // overlap units
-        v4u halo[K][H];
-        // round 0 (and 1), then the steady state from round 2
-        stage_round<K, LINE>(pa, xb, lane);
-        grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
-        if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
-        walk_round<K, LINE, MODE, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
-        if (rlast >= 1) {
-            stage_round<K, LINE>(pb, xb, lane);
-            if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
-            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
-            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
-                                             p);
-        }
-        for (int r = 2; r < R; r += 2) {
-            stage_round<K, LINE>(pa, xb, lane);
-            if (LINE == 128)
-                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
-            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
-                                             acc, wl, p);
-            if (r + 1 > rlast) break;
-            stage_round<K, LINE>(pb, xb, lane);
-            if (LINE == 64)
-                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
-            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
-            walk_round<K, LINE, MODE, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
-                                             r + 1 == rlast ? lastlen : LINE, acc, wl, p);
-        }
-        // the overlap, from registers, then (m > 65) the rest of it from memory
-        const uint32_t hb = uint32_t(p.S);
-        uint32_t extra = 0;
-#pragma unroll
-        for (int u = 0; u < H; ++u) {
-            if (u < hu) {
-                v4u t[K];
-#pragma unroll
-                for (int s = 0; s < K; ++s) t[s] = halo[s][u];
-                const uint32_t nv = m - 1 - 16u * u;
-                walk_overlap_unit<K, MODE>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
-            }
-        }
-        for (int u = H; u < hu; ++u) {
-            v4u t[K];
-#pragma unroll
-            for (int s = 0; s < K; ++s)
-                t[s] = *reinterpret_cast<const v4u *>(p.text + (g0 + s * kWave + lane + 1) * p.S + 16 * u);
-            const uint32_t nv = m - 1 - 16u * u;
-            walk_overlap_unit<K, MODE>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
-        }
-        if (MODE == kCount && K == 1) {
-            // the overlap's hits, summed over the wave
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) extra += uint32_t(__shfl_xor(int(extra), o));
-            acc = uint32_t(__builtin_amdgcn_readfirstlane(int(acc))) +
-                  uint32_t(__builtin_amdgcn_readfirstlane(int(extra)));
-        }
-    } else {
-        v4u pf[K][G::U];
-        fetch_round<K, LINE, true>(pf, p.text, p.n, g0 * p.S, p.S, lane_off, 0);
-        for (int r = 0; r < p.rounds; ++r) {
-            stage_round<K, LINE>(pf, xb, lane);
-            if (r + 1 < p.rounds) fetch_round<K, LINE, true>(pf, p.text, p.n, g0 * p.S, p.S, lane_off, r + 1);
-            walk_round<K, LINE, MODE, true>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
-        }
-    }
+    walk_wave<K, LINE, MODE == kCountPerWave ? int(kCount) : MODE, H>(p, xb, lane, g0, m, lane_off, q, acc, wl);
 
     if (MODE == kPositions) return;
+
+    if (MODE == kCountPerWave && lane == 0 && g0 < p.nwalks) p.walk_count[g0 / (kWave * K)] = acc;
 
     if (MODE == kCountPerWalk) {
         uint32_t c = 0;
@@ -484,7 +506,7 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     if (threadIdx.x == 0) {
         unsigned long long sum = 0;
         for (int w = 0; w < nwaves; ++w) sum += red[w];
-        if (MODE == kCountPerWalk) {
+        if (MODE == kCountPerWalk || MODE == kCountPerWave) {
             p.wg_part[blockIdx.x] = sum;
             uint32_t mask = 0;
             for (int w = 0; w < nwaves; ++w) mask |= red[w] ? 1u << w : 0u;
@@ -713,6 +735,99 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
     }
 }
 
+// Per-wave plans: one thread per counting wave, kPlaceThreads waves of whole
+// counting workgroups per block (per_block of them, wpg waves each): the
+// output slot of every wave with a match, from the same two-level prefix.
+__global__ __launch_bounds__(kPlaceThreads) void k_place_waves(const uint32_t *wave_count,
+                                                               const unsigned long long *part,
+                                                               const unsigned long long *sup, int64_t nwaves,
+                                                               int wpg, int per_block, int64_t *wave_off) {
+    __shared__ unsigned long long sh[kPlaceThreads / kWave];
+    const int t = threadIdx.x;
+    const int64_t wg0 = int64_t(blockIdx.x) * per_block;
+    const int64_t w = wg0 * wpg + t;
+    const uint32_t c = (t < per_block * wpg && w < nwaves) ? wave_count[w] : 0u;
+    const int64_t sb = wg0 / kSuper * kSuper;
+    unsigned long long before = 0;
+    for (int64_t i = sb + t; i < wg0; i += kPlaceThreads) before += part[i];
+    const int64_t base = int64_t(sup[wg0 / kSuper] + block_sum(before, sh));
+    unsigned long long total;
+    const unsigned long long ex = block_exclusive_scan(c, sh, &total);
+    if (c) wave_off[w] = base + int64_t(ex);
+}
+
+// Positions of per-wave plans.  One workgroup of kRewalkThreads per counting
+// workgroup; it leaves at once unless one of its waves had a match.  Each
+// such wave's 64 spans (64 S bytes from the wave's first walk) are split over
+// the threads, each walking its share of S / 4 bytes plus the m - 1 bytes
+// after it twice from the start state: once counting the matches that start
+// in its share, once writing them from its output slot (the wave's slot plus
+// a block scan of the counts).  A lone wave walking its own 64 spans twice
+// would leave its result waiting on two serial walks of S + m - 1 bytes.
+// The table is read through a pointer into dynamic LDS (the block scan's
+// slots follow it there), the text with 4-byte loads.
+constexpr int kRewalkThreads = 256;
+
+// One thread's share: the matches starting in [a, b), walking bytes
+// [a, min(n, b + m - 1)) from the start state (a match ends m - 1 bytes after
+// it starts; from the start state at a, no match that starts before a can be
+// completed).  WRITE: the k-th of them goes to positions[off + k] (below cap).
+// a is a multiple of 4.
+template <bool WRITE>
+__device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n, const unsigned char *tab, uint32_t m,
+                                                 int64_t a, int64_t b, int64_t off, int64_t *positions, int64_t cap) {
+    const int64_t lim = b + int64_t(m) - 1 < n ? b + int64_t(m) - 1 : n;
+    uint32_t q = 0, c = 0;
+    for (int64_t j0 = a; j0 < lim; j0 += 4) {
+        uint32_t w;
+        if (j0 + 4 <= n) {
+            w = *reinterpret_cast<const uint32_t *>(text + j0);
+        } else {
+            w = 0;
+            for (int k = 0; j0 + k < n; ++k) w |= uint32_t(text[j0 + k]) << (8 * k);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            q = tab[q * uint32_t(kRow) + ((w >> (8 * k)) & 0xffu)];
+            if (q == m && j0 + k < lim) {
+                if (WRITE && off + c < cap) positions[off + c] = j0 + k - int64_t(m - 1);
+                ++c;
+            }
+        }
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, int64_t n, const uint8_t *table,
+                                                           int32_t m, int64_t S, int wpg, const uint32_t *wg_waves,
+                                                           const int64_t *wave_off, int64_t *positions, int64_t cap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t mask = wg_waves[blockIdx.x];
+    if (mask == 0) return;
+    const int t = threadIdx.x;
+    {
+        const uint32_t *tg = reinterpret_cast<const uint32_t *>(table);
+        const int words = (m + 1) * (DFA_ALPHABET / 4);
+        for (int i = t; i < words; i += kRewalkThreads)
+            *reinterpret_cast<uint32_t *>(smem + (i >> 6) * kRow + 4 * (i & 63)) = tg[i];
+    }
+    unsigned long long *sh = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(m));
+    __syncthreads();
+    const int64_t share = kWave * S / kRewalkThreads;  // S is a multiple of 16
+    for (int w = 0; w < wpg; ++w) {
+        if (((mask >> w) & 1u) == 0) continue;  // uniform over the workgroup
+        const int64_t gw = int64_t(blockIdx.x) * wpg + w;
+        const int64_t start = gw * kWave * S;
+        const int64_t end = start + kWave * S < n ? start + kWave * S : n;
+        const int64_t a = start + t * share;
+        const int64_t b = a + share < end ? a + share : end;
+        const uint32_t c = a < b ? rewalk_share<false>(text, n, smem, uint32_t(m), a, b, 0, nullptr, 0) : 0u;
+        unsigned long long total;
+        const int64_t off = wave_off[gw] + int64_t(block_exclusive_scan(c, sh, &total));
+        if (c) rewalk_share<true>(text, n, smem, uint32_t(m), a, b, off, positions, cap);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side: planning and the C ABI
 // ---------------------------------------------------------------------------
@@ -732,7 +847,11 @@ template <int K, int LINE, int H>
 const void *scan_fn(int mode) {
     if (mode == kCount) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCount, H>);
     if (mode == kCountPerWalk) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWalk, H>);
-    return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions, H>);
+    if (mode == kPositions) return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions, H>);
+    if constexpr (K == 1 && H >= 2) {
+        if (mode == kCountPerWave) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWave, H>);
+    }
+    return nullptr;
 }
 
 // the (walks per lane, bytes per round) shapes compiled into the library, each
@@ -750,6 +869,14 @@ const void *pick_scan(int K, int line, int mode, int m) {
 // buffer per wave and, where the per-walk counting pass stages its records,
 // 1 KiB more per wave (the positions pass runs with the same plan and size).
 bool plan_stages(int K, int m, int mode) { return stages_records(K, mode, halo_units_for(m)) && m <= kStageMaxM; }
+
+// Positions plans for patterns longer than 17 bytes, one walk per lane, count
+// per wave: their walk is the count-only one (with per-walk counts and
+// records it needs more registers than 6 waves per SIMD leave, and at m > 33
+// it spills), and matches that long are rarely dense, so that walking the
+// waves with a match a second and third time costs less than per-walk
+// bookkeeping in every wave.
+bool per_wave_plan(int K, int m) { return K == 1 && halo_units_for(m) >= 2; }
 
 size_t scan_lds_bytes(int wpg, int K, int line, int m, int mode) {
     const bool rec = plan_stages(K, m, mode);
@@ -1005,8 +1132,11 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
         return DFA_OK;
     }
 
+    const int K = (tune && tune->chains_per_lane) ? tune->chains_per_lane : kDefaultK;
+    const bool per_wave = want_pos && per_wave_plan(K, m);
+    const int count_mode = !want_pos ? kCount : per_wave ? kCountPerWave : kCountPerWalk;
     Plan pl;
-    if (!make_plan(n, m, want_pos ? kCountPerWalk : kCount, tune, pl)) return DFA_EHIP;
+    if (!make_plan(n, m, count_mode, tune, pl)) return DFA_EHIP;
     if (want_pos && pl.S > kMaxPositionsSpan) {
         dfa::set_error("dfa_count: positions need chain_bytes <= %lld", (long long)kMaxPositionsSpan);
         return DFA_EINVAL;
@@ -1047,11 +1177,32 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     }
 
     sp.walk_count = wcnt;
+    sp.wg_part = part;
+    sp.wg_waves = waves;
+    if (per_wave) {
+        // count per wave (walk_count / walk_off hold one entry per wave), then
+        // the waves with a match are walked again to write their positions
+        int rc = launch_walk(pl, kCountPerWave, sp, st);
+        if (rc != DFA_OK) return rc;
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part,
+                           pl.blocks, sup, count);
+        const int per_block = kPlaceThreads / pl.wpg;  // counting workgroups per placement block
+        hipLaunchKernelGGL(k_place_waves, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0,
+                           st, (const uint32_t *)wcnt, (const unsigned long long *)part,
+                           (const unsigned long long *)sup, dfa::ceil_div(nw, kWave), pl.wpg, per_block, woff);
+        if (!hip_ok(hipGetLastError(), "placement launch")) return DFA_EHIP;
+        const int rw_lds = table_lds_bytes(m) + kRewalkThreads / kWave * 8;
+        if (!dfa::allow_lds(reinterpret_cast<const void *>(&k_rewalk), table_lds_bytes(DFA_MAX_M) + 256))
+            return DFA_EHIP;
+        hipLaunchKernelGGL(k_rewalk, dim3(unsigned(pl.blocks)), dim3(kRewalkThreads), rw_lds, st, text, n, table, m,
+                           pl.S, pl.wpg, (const uint32_t *)waves, (const int64_t *)woff, positions, cap);
+        if (!hip_ok(hipGetLastError(), "k_rewalk launch")) return DFA_EHIP;
+        dfa::clear_error();
+        return DFA_OK;
+    }
     sp.stage = plan_stages(pl.K, m, kCountPerWalk) ? 1 : 0;
     sp.walk_buf = wbuf;
     sp.walk_buf1 = wbuf1;
-    sp.wg_part = part;
-    sp.wg_waves = waves;
     int rc = launch_walk(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part, pl.blocks,
