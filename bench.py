@@ -56,7 +56,7 @@ METRIC = "text GB/s (and % of HBM peak) single-pattern; pattern-bytes/s batched;
 HBM_PEAK_GBS = 8000.0
 PATTERN_LENGTHS = (4, 8, 16, 32, 64)
 SCAN_SOURCES = [os.path.join(ROOT, "paper_1506_08612_amd", "csrc", f) for f in ("dfa_scan.hip", "walk_common.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_perwalk_genome3200MB_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_textwalk_genome3200MB_traffic.txt")
 
 
 def log(*a):

@@ -143,6 +143,18 @@ def test_positions_truncated_to_cap():
     assert np.array_equal(pos.cpu().numpy(), np.arange(1000))
 
 
+def test_positions_truncated_to_cap_long_pattern():
+    """Patterns longer than 17 bytes count per wave and write positions from a second walk
+    of the waves with a match; the cap holds there too, and the count stays exact."""
+    text = np.full(300_000, ord("G"), np.uint8)
+    d = api.to_device(text)
+    for m in (18, 40, 100):
+        tab, mm = api.device_table(b"G" * m)
+        c, pos = api.positions(d, tab, mm, cap=1234)
+        assert c == text.size - m + 1
+        assert np.array_equal(pos.cpu().numpy(), np.arange(1234))
+
+
 def test_repeatable_bit_equal():
     text = gc_text(5_000_000, 3)
     d = api.to_device(text)
