@@ -15,8 +15,12 @@ Also reported:
   same steps right after the timed one (an event between two launches leaves
   the stream idle for ~10-15 us, so the timed steps carry none); algorithmic
   bytes = the text read once; the count-only scan is timed beside it;
+* read_reduce_GBps -- a trivial read-reduce over the same device buffer (torch's
+  sum of its 8-byte words), the streaming-read rate reached in the same run, and
+  both scans' fractions of it;
 * cpu_baseline -- the CPU oracle (plain C, one thread) timed on a bounded
-  prefix of the same text for the same five patterns;
+  prefix of the same text for the same five patterns; the batched and
+  segmented legs carry their own, job-parallel over the host's cores;
 * per-pattern latency p50/p99 of the full call (events around each call, in the
   second run of the steps);
 * batched -- 1 GB GC-41% text x 1024 patterns (lengths 4..64, half drawn from
@@ -108,6 +112,35 @@ def _events_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def cpu_pairs_baseline(text, seg_off, patterns, pair_seg, pair_pat, budget):
+    """The oracle's per-(segment, pattern) count, job-parallel over the host's cores (one
+    single-thread scan per job, on threads: the C call releases the interpreter lock), on the
+    segments that start within the first `budget` bytes.  Returns pattern-bytes/s and what
+    was scanned."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    seg_off = np.asarray(seg_off, np.int64)
+    pair_seg, pair_pat = np.asarray(pair_seg, np.int64), np.asarray(pair_pat, np.int64)
+    if seg_off.size == 2:  # one text: its prefix
+        end = int(min(budget, seg_off[1]))
+        so, keep = np.array([0, end], np.int64), np.ones(pair_seg.size, bool)
+    else:
+        nseg = max(1, int(np.searchsorted(seg_off, budget, side="right")) - 1)
+        so, keep = seg_off[:nseg + 1], pair_seg < nseg
+    sample = np.ascontiguousarray(text[:int(so[-1])])
+    ps, pp = pair_seg[keep], pair_pat[keep]
+    cores = len(os.sched_getaffinity(0))
+    jobs = np.array_split(np.arange(ps.size), cores)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda idx: oracle.pair_counts(sample, so, patterns, ps[idx], pp[idx]), jobs))
+    wall = time.perf_counter() - t0
+    pb = int(np.diff(so)[ps].sum())
+    return {"value": round(pb / wall, 1), "unit": "pattern-bytes/s", "cores": cores, "kind": "oracle",
+            "sample": f"{so.size - 1} segment(s), {int(so[-1])} B, {ps.size} (segment, pattern) pairs, "
+                      f"job-parallel over {cores} threads, {wall:.1f} s on {cpu_model()}"}
+
+
 def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
     from paper_1506_08612_amd import autotune, graph
     log(f"batched: {n} bytes x {npat} patterns")
@@ -135,6 +168,7 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
     sep_ms = _events_ms(torch, lambda: sb.run(d), 1)
     sep_equal = bool(np.array_equal(sb.counts.cpu().numpy()[:npat], ref))
     deg = bench_degenerate(torch, api, d, n)
+    cpu = cpu_pairs_baseline(w.text, [0, n], w.patterns, pair_seg, pair_pat, 24_000_000)
     pb = n * npat
     return deg, {"workload": f"gc41 text {n} B x {npat} patterns m=U[4,64] (half drawn), per-pattern counts",
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1),
@@ -146,7 +180,8 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
             "items": int(b.plan.nitems), "counts_equal_one_per_launch": equal,
             "separate_automata": {"ms": round(sep_ms, 3), "pattern_bytes_per_s": round(pb / (sep_ms * 1e-3), 1),
                                   "speedup_vs_one_per_launch": round(base_ms / sep_ms, 2),
-                                  "counts_equal_one_per_launch": sep_equal}}
+                                  "counts_equal_one_per_launch": sep_equal},
+            "cpu_baseline": cpu}
 
 
 def bench_degenerate(torch, api, d, n):
@@ -275,11 +310,13 @@ def bench_segmented(torch, api, synth):
     equal = bool(np.array_equal(b.counts.cpu().numpy(), sb.counts.cpu().numpy()))
     seg_len = np.diff(w.seg_off)
     pb = int(seg_len[w.pair_seg].sum())
+    cpu = cpu_pairs_baseline(w.text, w.seg_off, w.patterns, w.pair_seg, w.pair_pat, 600_000_000)
     return {"workload": f"{seg_len.size} segments, {int(w.seg_off[-1])} B, {w.pair_seg.size} (segment, pattern) pairs",
             "ms": round(ms, 3), "text_GBps": round(int(w.seg_off[-1]) / ms / 1e6, 1),
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems),
             "method": "merged automata per segment, HIP graph replay",
-            "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal}
+            "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal,
+            "cpu_baseline": cpu}
 
 
 def bench_serving(torch, nq, warm=50, pool=64):
@@ -453,6 +490,12 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         kern[len(p)] = e0.elapsed_time(e1) / a.kernel_reps
     count_only_gbs = n / (float(np.mean(list(kern.values()))) * 1e-3) / 1e9
+    # a trivial read-reduce over the same buffer (torch's sum of its 8-byte words): the
+    # streaming-read rate this device reaches in the same run
+    words = dtext[:n // 8 * 8].view(torch.int64)
+    red_ms = _events_ms(torch, lambda: words.sum(), 5)
+    read_gbs = (n // 8 * 8) / (red_ms * 1e-3) / 1e9
+    del words
     walk_avg_ms = float(np.mean([x for w in walk_ms for x in w]))
     achieved = n / (walk_avg_ms * 1e-3) / 1e9
     traffic = read_traffic()
@@ -528,11 +571,15 @@ def main(argv=None) -> int:
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
         "latency_ms": {"p50": round(float(np.percentile(lat_all, 50)), 4),
                        "p99": round(float(np.percentile(lat_all, 99)), 4),
+                       "min": round(float(np.min(lat_all)), 4),
                        "per_pattern_p50": {str(len(p)): round(float(np.percentile(lat[i], 50)), 4)
                                            for i, p in enumerate(pats)}},
         "walk_kernel_ms": {str(len(p)): round(float(np.mean(walk_ms[i])), 4) for i, p in enumerate(pats)},
         "count_only_kernel_ms": {str(k): round(v, 4) for k, v in kern.items()},
         "count_only_frac": round(count_only_gbs / HBM_PEAK_GBS, 4),
+        "read_reduce_GBps": round(read_gbs, 1),
+        "frac_of_read_reduce": {"text_walk": round(achieved / read_gbs, 4),
+                                "count_only": round(count_only_gbs / read_gbs, 4)},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_scan text walk of count + positions (per-walk counts for m <= 17, per-wave counts above)",
