@@ -720,7 +720,9 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
     __syncthreads();
     if (t < per_block && wg0 + t < nb) wg_flag[wg0 + t] = over[t];
     for (uint32_t k = t; k < nbuf; k += kPlaceThreads) {
-        // the walk holding buffered match k: the last w with first[w] <= k
+        // the walk holding buffered match k: the last w with first[w] <= k.
+        // Consecutive threads write consecutive positions (a thread writing a
+        // run of its own would scatter partial lines across the wave).
         int lo = 0, hi = bw - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
@@ -848,7 +850,7 @@ const void *scan_fn(int mode) {
     if (mode == kCount) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCount, H>);
     if (mode == kCountPerWalk) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWalk, H>);
     if (mode == kPositions) return reinterpret_cast<const void *>(&k_scan<K, LINE, kPositions, H>);
-    if constexpr (K == 1 && H >= 2) {
+    if constexpr (K == 1) {
         if (mode == kCountPerWave) return reinterpret_cast<const void *>(&k_scan<K, LINE, kCountPerWave, H>);
     }
     return nullptr;
@@ -870,13 +872,16 @@ const void *pick_scan(int K, int line, int mode, int m) {
 // 1 KiB more per wave (the positions pass runs with the same plan and size).
 bool plan_stages(int K, int m, int mode) { return stages_records(K, mode, halo_units_for(m)) && m <= kStageMaxM; }
 
-// Positions plans for patterns longer than 17 bytes, one walk per lane, count
-// per wave: their walk is the count-only one (with per-walk counts and
-// records it needs more registers than 6 waves per SIMD leave, and at m > 33
-// it spills), and matches that long are rarely dense, so that walking the
-// waves with a match a second and third time costs less than per-walk
-// bookkeeping in every wave.
-bool per_wave_plan(int K, int m) { return K == 1 && halo_units_for(m) >= 2; }
+// Positions plans for patterns of at least kPerWaveMinM bytes, one walk per
+// lane, count per wave: their walk is the count-only one (per-walk counts and
+// records cost registers, i.e. resident waves, and at m > 33 spill), and such
+// matches are rarely dense -- on a 4-letter text a 12-mer is expected once per
+// 4^12 ~ 17 million bytes, one wave's 32 KiB of spans in ~500 -- so walking
+// the few waves with a match twice more costs less than per-walk bookkeeping
+// in every wave.  Shorter patterns keep the per-walk plan: an 8-mer lands in
+// about every second wave.
+constexpr int kPerWaveMinM = 12;
+bool per_wave_plan(int K, int m) { return K == 1 && m >= kPerWaveMinM; }
 
 size_t scan_lds_bytes(int wpg, int K, int line, int m, int mode) {
     const bool rec = plan_stages(K, m, mode);
