@@ -365,7 +365,7 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--study", action="store_true",
                     help="also run the size sweep and workgroup load-balance study of the scan")
-    ap.add_argument("--only", choices=("batched", "segmented", "serving"),
+    ap.add_argument("--only", choices=("batched", "segmented", "serving", "fasta"),
                     help="run only this leg and print its figures (for profiling)")
     a = ap.parse_args(argv)
 
@@ -380,8 +380,13 @@ def main(argv=None) -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if a.only:
+        def fasta_leg():
+            w = synth.paper_scale(n=a.n, ms=PATTERN_LENGTHS)
+            return bench_fasta(torch, api, w.text, api.to_device(w.text))
+
         legs = {"batched": lambda: bench_batched(torch, api, synth)[1],
                 "segmented": lambda: bench_segmented(torch, api, synth),
+                "fasta": fasta_leg,
                 "serving": lambda: bench_serving(torch, a.serve_queries)}
         print(json.dumps({a.only: legs[a.only]()}), flush=True)
         return 0

@@ -302,11 +302,9 @@ int64_t dfa_fasta_workspace_bytes(int64_t n);
 
 /* Device-only.  Turns FASTA text raw[0..n-1] (device, 4-byte aligned) into
  * plain sequence: a line whose first byte is '>' is a header (it starts a
- * record; none of its bytes are kept); every other byte is kept except '
-'
- * and '
-', with 'a'..'z' made upper case (soft-masking dropped).
- *   out        device, room for n bytes: the kept bytes, in order
+ * record; none of its bytes are kept); every other byte is kept except '\n'
+ * and '\r', with 'a'..'z' made upper case (soft-masking dropped).
+ *   out        device, room for n bytes, 4-byte aligned: the kept bytes, in order
  *   rec_start  device int64, room for rec_cap entries: where each record's
  *              sequence starts in `out` (the first rec_cap records)
  *   totals     device int64[2]: {kept bytes, records} (exact even past rec_cap)

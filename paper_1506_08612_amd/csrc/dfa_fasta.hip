@@ -11,17 +11,22 @@
 // Whether a byte is kept depends on the first byte of its line, which may lie
 // far back, so the text is cut into 64 KiB chunks and processed in three
 // passes:
-//   A  per chunk: its last newline, its header starts, and its kept bytes --
-//      those before its first newline counted apart, as their line may have
-//      started in an earlier chunk;
-//   B  one workgroup: the line each chunk starts in (the last newline of all
-//      earlier chunks), hence its kept bytes, and the chunk's output and
+//   A  per chunk: its last line start (with whether that line is a header),
+//      its header count, and its kept bytes -- those before its first line
+//      start counted apart, as their line began in an earlier chunk;
+//   B  one workgroup: the line each chunk starts in (the last line start of
+//      all earlier chunks), hence its kept bytes, and the chunk's output and
 //      record offsets (prefix sums);
 //   C  per chunk again: the kept bytes written, compacted, at their offsets,
 //      and the record starts.
-// Within a chunk a workgroup of 256 threads takes 1 KiB per round, 4 bytes
-// per thread (one coalesced dword load); block scans carry the last newline
-// (prefix max) and the kept and header counts (prefix sums) across threads.
+// A line start s is carried as 2 s + (byte s is '>'), so that one prefix max
+// over line starts gives both where the current line began and whether it is
+// a header, with no load of that byte.  Within a chunk a workgroup of 256
+// threads takes 4 KiB per round, 16 bytes per thread (four dword loads;
+// consecutive threads read consecutive 16-byte pieces, and the byte before a
+// wave's first piece comes with them); per round one block scan carries the
+// line start (prefix max) and one the kept and header counts (prefix sums,
+// packed in 64 bits).
 
 #include <hip/hip_runtime.h>
 
@@ -36,22 +41,26 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaveSize = 64;
-constexpr int kRound = kThreads * 4;  // bytes per round
-constexpr int64_t kChunk = 64 * 1024;  // bytes per workgroup
+constexpr int kPer = 16;                 // bytes per thread per round
+constexpr int kRound = kThreads * kPer;  // bytes per round
+constexpr int64_t kChunk = 64 * 1024;    // bytes per workgroup
+constexpr int kPlanThreads = 1024;
 
 struct ChunkSummary {
-    int64_t last_nl;     // position of the chunk's last '\n', or -1
-    uint32_t pre;        // bytes before its first '\n' that would be kept in a sequence line
-    uint32_t kept;       // kept bytes after its first '\n'
+    int64_t last_ls;     // last line start in the chunk, as 2 s + header, or -1
+    uint32_t pre;        // bytes before its first line start that a sequence line would keep
+    uint32_t kept;       // kept bytes from its first line start on
     uint32_t headers;    // header lines starting in the chunk
     uint32_t pad;
 };
 
 struct ChunkPlan {
-    int64_t nl_before;   // last '\n' before the chunk, or -1
+    int64_t ls_before;   // last line start before the chunk (2 s + header), or -1
     int64_t out_off;     // kept bytes before the chunk
     int64_t rec_off;     // records before the chunk
 };
+
+constexpr uint32_t kNl = '\n', kCr = '\r', kGt = '>';
 
 __device__ __forceinline__ int64_t wave_incl_max(int64_t v) {
     const int lane = threadIdx.x & (kWaveSize - 1);
@@ -73,17 +82,18 @@ __device__ __forceinline__ unsigned long long wave_incl_sum(unsigned long long v
     return v;
 }
 
-// exclusive prefix max over the block, seeded with `carry`; *all = block max (and carry)
+// exclusive prefix max over the block (any multiple of 64 threads up to
+// 1024), seeded with `carry`; *all = block max (and carry)
 __device__ __forceinline__ int64_t block_excl_max(int64_t v, int64_t carry, int64_t *sh, int64_t *all) {
     const int lane = threadIdx.x & (kWaveSize - 1), w = threadIdx.x / kWaveSize;
+    const int nw = blockDim.x / kWaveSize;
     const int64_t inc = wave_incl_max(v);
     int64_t ex = __shfl_up(inc, 1);
     if (lane == 0) ex = -1;
     if (lane == kWaveSize - 1) sh[w] = inc;
     __syncthreads();
     int64_t before = carry, tot = carry;
-#pragma unroll
-    for (int i = 0; i < kThreads / kWaveSize; ++i) {
+    for (int i = 0; i < nw; ++i) {
         if (i < w) before = sh[i] > before ? sh[i] : before;
         tot = sh[i] > tot ? sh[i] : tot;
     }
@@ -92,16 +102,17 @@ __device__ __forceinline__ int64_t block_excl_max(int64_t v, int64_t carry, int6
     return ex > before ? ex : before;
 }
 
-// exclusive prefix sum over the block; *all = block total
+// exclusive prefix sum over the block (any multiple of 64 threads up to 1024);
+// *all = block total
 __device__ __forceinline__ unsigned long long block_excl_sum(unsigned long long v, unsigned long long *sh,
                                                              unsigned long long *all) {
     const int lane = threadIdx.x & (kWaveSize - 1), w = threadIdx.x / kWaveSize;
+    const int nw = blockDim.x / kWaveSize;
     const unsigned long long inc = wave_incl_sum(v);
     if (lane == kWaveSize - 1) sh[w] = inc;
     __syncthreads();
     unsigned long long before = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < kThreads / kWaveSize; ++i) {
+    for (int i = 0; i < nw; ++i) {
         if (i < w) before += sh[i];
         tot += sh[i];
     }
@@ -110,25 +121,45 @@ __device__ __forceinline__ unsigned long long block_excl_sum(unsigned long long 
     return before + inc - v;
 }
 
-// The thread's 4 bytes of a round (positions p .. p+3); bytes at or past n are
-// absent (value 0x100).
-__device__ __forceinline__ void load4(const uint8_t *raw, int64_t n, int64_t p, uint32_t (&b)[4]) {
-    if (p + 4 <= n) {
-        const uint32_t w = *reinterpret_cast<const uint32_t *>(raw + p);
+// The thread's kPer bytes of a round (positions p .. p+kPer-1; p is a multiple
+// of 4, raw 4-byte aligned), bytes at or past n absent (value 0x100), and
+// whether a line starts at each of them: at position 0, or after a '\n' (the
+// byte before the piece comes from the previous lane, or from memory for a
+// wave's first lane).
+__device__ __forceinline__ uint32_t load_piece(const uint8_t *raw, int64_t n, int64_t p, uint32_t (&b)[kPer]) {
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const uint32_t mem_before = lane == 0 ? (p == 0 ? kNl : (p - 1 < n ? uint32_t(raw[p - 1]) : 0x100u)) : 0u;
+    if (p + kPer <= n) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = (w >> (8 * j)) & 0xffu;
+        for (int q = 0; q < kPer / 4; ++q) {
+            const uint32_t w = *reinterpret_cast<const uint32_t *>(raw + p + 4 * q);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[4 * q + j] = (w >> (8 * j)) & 0xffu;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = p + j < n ? raw[p + j] : 0x100u;
+        for (int j = 0; j < kPer; ++j) b[j] = p + j < n ? raw[p + j] : 0x100u;
     }
+    uint32_t before = uint32_t(__shfl_up(int(b[kPer - 1]), 1));
+    if (lane == 0) before = mem_before;
+    uint32_t starts = 0;  // bit j: a line starts at p + j
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t prev = j ? b[j - 1] : before;
+        if (prev == kNl && b[j] <= 0xffu) starts |= 1u << j;
+    }
+    return starts;
 }
 
-constexpr uint32_t kNl = '\n', kCr = '\r', kGt = '>';
-
-// Is the byte before position p a newline (or p the start of the text)?
-__device__ __forceinline__ bool line_starts_at(const uint8_t *raw, int64_t p, const uint32_t (&b)[4], int j) {
-    if (j > 0) return b[j - 1] == kNl;
-    return p == 0 || raw[p - 1] == kNl;
+// The last line start among the piece's bytes (2 s + header), or -1.
+__device__ __forceinline__ int64_t last_start(int64_t p, const uint32_t (&b)[kPer], uint32_t starts) {
+    if (!starts) return -1;
+    const int j = 31 - __clz(starts);
+    int64_t v = -1;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (k == j) v = 2 * (p + k) + (b[k] == kGt ? 1 : 0);
+    return v;
 }
 
 // Pass A
@@ -137,49 +168,40 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
     __shared__ unsigned long long shs[kThreads / kWaveSize];
     const int64_t c0 = int64_t(blockIdx.x) * kChunk;
     const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    int64_t carry_nl = -1;  // last '\n' inside the chunk so far
+    int64_t carry = -1;  // last line start inside the chunk so far
     unsigned long long pre = 0, kept = 0, headers = 0;
     for (int64_t r0 = c0; r0 < c1; r0 += kRound) {
-        const int64_t p = r0 + 4 * int64_t(threadIdx.x);
-        uint32_t b[4];
-        load4(raw, c1, p, b);
-        int64_t mine = -1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (b[j] == kNl) mine = p + j;
+        const int64_t p = r0 + kPer * int64_t(threadIdx.x);
+        uint32_t b[kPer];
+        const uint32_t starts = load_piece(raw, c1, p, b);
         int64_t all;
-        int64_t nl = block_excl_max(mine, carry_nl, shm, &all);
-        carry_nl = all;
-        // the line state at the thread's first byte, when its line starts inside the chunk
-        bool hdr = nl >= 0 && nl + 1 < c1 && raw[nl + 1] == kGt;
-        unsigned long long my_pre = 0, my_kept = 0, my_hdr = 0;
+        int64_t cur = block_excl_max(last_start(p, b, starts), carry, shm, &all);
+        carry = all;
+        // pre, kept and header counts of the thread, packed 21 bits apart (each < 2^21)
+        unsigned long long packed = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kPer; ++j) {
             const uint32_t x = b[j];
             if (x > 0xffu) continue;
-            if (x == kGt && line_starts_at(raw, p + j, b, j)) ++my_hdr;
-            if (x == kNl) {
-                nl = p + j;
-                hdr = j + 1 < 4 ? b[j + 1] == kGt : (p + 4 < c1 && raw[p + 4] == kGt);
-                continue;
+            if ((starts >> j) & 1u) {
+                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
+                if (x == kGt) ++packed;
             }
-            if (x == kCr) continue;
-            if (nl < 0)
-                ++my_pre;
-            else if (!hdr)
-                ++my_kept;
+            if (x == kNl || x == kCr) continue;
+            if (cur < 0)
+                packed += 1ull << 42;
+            else if (!(cur & 1))
+                packed += 1ull << 21;
         }
         unsigned long long t;
-        block_excl_sum(my_pre, shs, &t);
-        pre += t;
-        block_excl_sum(my_kept, shs, &t);
-        kept += t;
-        block_excl_sum(my_hdr, shs, &t);
-        headers += t;
+        block_excl_sum(packed, shs, &t);
+        pre += t >> 42;
+        kept += (t >> 21) & 0x1fffffu;
+        headers += t & 0x1fffffu;
     }
     if (threadIdx.x == 0) {
         ChunkSummary s;
-        s.last_nl = carry_nl;
+        s.last_ls = carry;
         s.pre = uint32_t(pre);
         s.kept = uint32_t(kept);
         s.headers = uint32_t(headers);
@@ -188,40 +210,46 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
     }
 }
 
-// Pass B: one workgroup over all chunks
-__global__ __launch_bounds__(kThreads) void k_fasta_plan(const uint8_t *raw, int64_t n, const ChunkSummary *sum,
-                                                         int64_t nchunks, ChunkPlan *plan, int64_t *totals) {
-    __shared__ int64_t shm[kThreads / kWaveSize];
-    __shared__ unsigned long long shs[kThreads / kWaveSize];
-    int64_t carry_nl = -1;
-    unsigned long long out = 0, rec = 0;
-    for (int64_t base = 0; base < nchunks; base += kThreads) {
-        const int64_t c = base + threadIdx.x;
-        const bool ok = c < nchunks;
-        const ChunkSummary s = ok ? sum[c] : ChunkSummary{-1, 0, 0, 0, 0};
-        int64_t all;
-        const int64_t before = block_excl_max(s.last_nl, carry_nl, shm, &all);
-        carry_nl = all;
-        // the line the chunk starts in begins right after `before`
-        const int64_t ls = before + 1;
-        const bool hdr = ok && ls < n && raw[ls] == kGt;
-        const unsigned long long kept = ok ? (hdr ? 0ull : s.pre) + s.kept : 0ull;
-        unsigned long long tk, th;
-        const unsigned long long ok_off = block_excl_sum(kept, shs, &tk);
-        const unsigned long long rec_off = block_excl_sum(ok ? s.headers : 0u, shs, &th);
-        if (ok) {
-            ChunkPlan cp;
-            cp.nl_before = before;
-            cp.out_off = int64_t(out + ok_off);
-            cp.rec_off = int64_t(rec + rec_off);
-            plan[c] = cp;
-        }
-        out += tk;
-        rec += th;
+// Pass B: one workgroup of kPlanThreads, each thread a run of consecutive
+// chunks: the last line start before each chunk (prefix max), then its kept
+// bytes and the output and record offsets (prefix sums).
+__global__ __launch_bounds__(kPlanThreads) void k_fasta_plan(const ChunkSummary *sum, int64_t nchunks,
+                                                             ChunkPlan *plan, int64_t *totals) {
+    __shared__ int64_t shm[kPlanThreads / kWaveSize];
+    __shared__ unsigned long long shs[kPlanThreads / kWaveSize];
+    const int64_t per = (nchunks + kPlanThreads - 1) / kPlanThreads;
+    const int64_t i0 = int64_t(threadIdx.x) * per, i1 = i0 + per < nchunks ? i0 + per : nchunks;
+    int64_t run_max = -1;
+    for (int64_t c = i0; c < i1; ++c) run_max = sum[c].last_ls > run_max ? sum[c].last_ls : run_max;
+    int64_t all;
+    const int64_t before0 = block_excl_max(run_max, -1, shm, &all);
+    // the kept bytes and records of the run
+    unsigned long long kept = 0, recs = 0;
+    int64_t before = before0;
+    for (int64_t c = i0; c < i1; ++c) {
+        const ChunkSummary s = sum[c];
+        kept += (before >= 0 && (before & 1) ? 0ull : s.pre) + s.kept;
+        recs += s.headers;
+        before = s.last_ls > before ? s.last_ls : before;
+    }
+    unsigned long long tk, tr;
+    unsigned long long out = block_excl_sum(kept, shs, &tk);
+    unsigned long long rec = block_excl_sum(recs, shs, &tr);
+    before = before0;
+    for (int64_t c = i0; c < i1; ++c) {
+        const ChunkSummary s = sum[c];
+        ChunkPlan cp;
+        cp.ls_before = before;
+        cp.out_off = int64_t(out);
+        cp.rec_off = int64_t(rec);
+        plan[c] = cp;
+        out += (before >= 0 && (before & 1) ? 0ull : s.pre) + s.kept;
+        rec += s.headers;
+        before = s.last_ls > before ? s.last_ls : before;
     }
     if (threadIdx.x == 0) {
-        totals[0] = int64_t(out);
-        totals[1] = int64_t(rec);
+        totals[0] = int64_t(tk);
+        totals[1] = int64_t(tr);
     }
 }
 
@@ -233,53 +261,46 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
     const int64_t c0 = int64_t(blockIdx.x) * kChunk;
     const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
     const ChunkPlan cp = plan[blockIdx.x];
-    int64_t carry_nl = cp.nl_before;
+    int64_t carry = cp.ls_before;
     int64_t o = cp.out_off;
     int64_t rec = cp.rec_off;
     for (int64_t r0 = c0; r0 < c1; r0 += kRound) {
-        const int64_t p = r0 + 4 * int64_t(threadIdx.x);
-        uint32_t b[4];
-        load4(raw, c1, p, b);
-        int64_t mine = -1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (b[j] == kNl) mine = p + j;
+        const int64_t p = r0 + kPer * int64_t(threadIdx.x);
+        uint32_t b[kPer];
+        const uint32_t starts = load_piece(raw, c1, p, b);
         int64_t all;
-        int64_t nl = block_excl_max(mine, carry_nl, shm, &all);
-        carry_nl = all;
-        const bool hdr0 = nl + 1 < n && raw[nl + 1] == kGt;
+        const int64_t cur0 = block_excl_max(last_start(p, b, starts), carry, shm, &all);
+        carry = all;
         // kept bytes and header starts of the thread, packed as (kept << 32) | headers
-        bool hdr = hdr0;
+        int64_t cur = cur0;
         unsigned long long packed = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kPer; ++j) {
             const uint32_t x = b[j];
             if (x > 0xffu) continue;
-            if (x == kGt && line_starts_at(raw, p + j, b, j)) ++packed;
-            if (x == kNl) {
-                hdr = j + 1 < 4 ? b[j + 1] == kGt : (p + 4 < n && raw[p + 4] == kGt);
-                continue;
+            if ((starts >> j) & 1u) {
+                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
+                if (x == kGt) ++packed;
             }
-            if (x != kCr && !hdr) packed += 1ull << 32;
+            if (x != kNl && x != kCr && !(cur & 1)) packed += 1ull << 32;
         }
         unsigned long long tot;
         const unsigned long long ex = block_excl_sum(packed, shs, &tot);
         int64_t w = o + int64_t(ex >> 32);
         int64_t h = rec + int64_t(ex & 0xffffffffu);
-        hdr = hdr0;
+        cur = cur0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kPer; ++j) {
             const uint32_t x = b[j];
             if (x > 0xffu) continue;
-            if (x == kGt && line_starts_at(raw, p + j, b, j)) {
-                if (h < rec_cap) rec_start[h] = w;
-                ++h;
+            if ((starts >> j) & 1u) {
+                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
+                if (x == kGt) {
+                    if (h < rec_cap) rec_start[h] = w;
+                    ++h;
+                }
             }
-            if (x == kNl) {
-                hdr = j + 1 < 4 ? b[j + 1] == kGt : (p + 4 < n && raw[p + 4] == kGt);
-                continue;
-            }
-            if (x != kCr && !hdr) out[w++] = uint8_t(x - 'a' < 26u ? x - 0x20u : x);
+            if (x != kNl && x != kCr && !(cur & 1)) out[w++] = uint8_t(x - 'a' < 26u ? x - 0x20u : x);
         }
         o += int64_t(tot >> 32);
         rec += int64_t(tot & 0xffffffffu);
@@ -307,9 +328,9 @@ extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, 
         dfa::set_error("dfa_fasta_normalize: null argument or negative size");
         return DFA_EINVAL;
     }
-    if ((reinterpret_cast<uintptr_t>(raw) & 3) || (reinterpret_cast<uintptr_t>(totals) & 7) ||
-        (reinterpret_cast<uintptr_t>(rec_start) & 7)) {
-        dfa::set_error("dfa_fasta_normalize: raw must be 4-byte, totals and rec_start 8-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(raw) & 3) || (reinterpret_cast<uintptr_t>(out) & 3) ||
+        (reinterpret_cast<uintptr_t>(totals) & 7) || (reinterpret_cast<uintptr_t>(rec_start) & 7)) {
+        dfa::set_error("dfa_fasta_normalize: raw and out must be 4-byte, totals and rec_start 8-byte aligned");
         return DFA_EINVAL;
     }
     const int64_t need = dfa_fasta_workspace_bytes(n);
@@ -328,8 +349,7 @@ extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, 
     ChunkSummary *sum = reinterpret_cast<ChunkSummary *>(ws);
     ChunkPlan *plan = reinterpret_cast<ChunkPlan *>(ws + dfa::round_up(c * int64_t(sizeof(ChunkSummary)), 256));
     if (c > 0) hipLaunchKernelGGL(k_fasta_summary, dim3(unsigned(c)), dim3(kThreads), 0, st, raw, n, sum);
-    hipLaunchKernelGGL(k_fasta_plan, dim3(1), dim3(kThreads), 0, st, raw, n, (const ChunkSummary *)sum, c, plan,
-                       totals);
+    hipLaunchKernelGGL(k_fasta_plan, dim3(1), dim3(kPlanThreads), 0, st, (const ChunkSummary *)sum, c, plan, totals);
     if (c > 0)
         hipLaunchKernelGGL(k_fasta_write, dim3(unsigned(c)), dim3(kThreads), 0, st, raw, n, (const ChunkPlan *)plan,
                            out, rec_start, rec_cap);
