@@ -328,9 +328,9 @@ extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, 
         dfa::set_error("dfa_fasta_normalize: null argument or negative size");
         return DFA_EINVAL;
     }
-    if ((reinterpret_cast<uintptr_t>(raw) & 3) || (reinterpret_cast<uintptr_t>(out) & 3) ||
-        (reinterpret_cast<uintptr_t>(totals) & 7) || (reinterpret_cast<uintptr_t>(rec_start) & 7)) {
-        dfa::set_error("dfa_fasta_normalize: raw and out must be 4-byte, totals and rec_start 8-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(raw) & 3) || (reinterpret_cast<uintptr_t>(totals) & 7) ||
+        (reinterpret_cast<uintptr_t>(rec_start) & 7)) {
+        dfa::set_error("dfa_fasta_normalize: raw must be 4-byte, totals and rec_start 8-byte aligned");
         return DFA_EINVAL;
     }
     const int64_t need = dfa_fasta_workspace_bytes(n);
