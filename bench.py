@@ -587,7 +587,7 @@ def main(argv=None) -> int:
                                 "count_only": round(count_only_gbs / read_gbs, 4)},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_scan text walk of count + positions (per-walk counts for m <= 17, per-wave counts above)",
+            "kernel": "k_scan text walk of count + positions (per-walk counts for m < 12, per-wave counts from 12)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
