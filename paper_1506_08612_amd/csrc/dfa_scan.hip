@@ -774,28 +774,44 @@ constexpr int kRewalkThreads = 256;
 // [a, min(n, b + m - 1)) from the start state (a match ends m - 1 bytes after
 // it starts; from the start state at a, no match that starts before a can be
 // completed).  WRITE: the k-th of them goes to positions[off + k] (below cap).
-// a is a multiple of 4.
+// a is a multiple of 4.  The bytes come 16 at a time as four words, the next
+// 16 requested before the current ones are walked.
+__device__ __forceinline__ void rewalk_fetch(const uint8_t *text, int64_t n, int64_t j0, int64_t lim,
+                                             uint32_t (&w)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = j0 + 4 * k;
+        if (j >= lim) {
+            w[k] = 0;
+        } else if (j + 4 <= n) {
+            w[k] = *reinterpret_cast<const uint32_t *>(text + j);
+        } else {
+            uint32_t v = 0;
+            for (int i = 0; j + i < n; ++i) v |= uint32_t(text[j + i]) << (8 * i);
+            w[k] = v;
+        }
+    }
+}
+
 template <bool WRITE>
 __device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n, const unsigned char *tab, uint32_t m,
                                                  int64_t a, int64_t b, int64_t off, int64_t *positions, int64_t cap) {
     const int64_t lim = b + int64_t(m) - 1 < n ? b + int64_t(m) - 1 : n;
     uint32_t q = 0, c = 0;
-    for (int64_t j0 = a; j0 < lim; j0 += 4) {
-        uint32_t w;
-        if (j0 + 4 <= n) {
-            w = *reinterpret_cast<const uint32_t *>(text + j0);
-        } else {
-            w = 0;
-            for (int k = 0; j0 + k < n; ++k) w |= uint32_t(text[j0 + k]) << (8 * k);
-        }
+    uint32_t cur[4], nxt[4];
+    rewalk_fetch(text, n, a, lim, cur);
+    for (int64_t j0 = a; j0 < lim; j0 += 16) {
+        rewalk_fetch(text, n, j0 + 16, lim, nxt);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            q = tab[q * uint32_t(kRow) + ((w >> (8 * k)) & 0xffu)];
+        for (int k = 0; k < 16; ++k) {
+            q = tab[q * uint32_t(kRow) + ((cur[k / 4] >> (8 * (k % 4))) & 0xffu)];
             if (q == m && j0 + k < lim) {
                 if (WRITE && off + c < cap) positions[off + c] = j0 + k - int64_t(m - 1);
                 ++c;
             }
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cur[k] = nxt[k];
     }
     return c;
 }
