@@ -67,10 +67,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src: str) -> str:
+    """C/C++ source without its comments and with whitespace collapsed (string and
+    character literals kept): two sources with the same code_text compile alike."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(paths) -> str:
+    """Hash of the kernel sources' code (comments and layout do not count)."""
     h = hashlib.sha256()
     for p in paths:
-        h.update(open(p, "rb").read())
+        h.update(code_text(open(p, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

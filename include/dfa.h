@@ -90,8 +90,10 @@ int dfa_build(const uint8_t *pattern, int32_t m, uint8_t *table);
 /* ------------------------------------------------------------------------ */
 
 /* Device workspace needed by dfa_count for this (n, m, want_positions, tune):
- * 0 when want_positions == 0; otherwise the per-walk match counts and their
- * prefix sums.  Returns bytes, or DFA_EINVAL. */
+ * 0 when want_positions == 0; otherwise per walk (or per wave of 64 walks)
+ * its match count, output offset and first 16 match starts, and per
+ * workgroup its total, flags and a prefix level (about 44 bytes per walk of
+ * 512 text bytes).  Returns bytes, or DFA_EINVAL. */
 int64_t dfa_count_workspace_bytes(int64_t n, int32_t m, int32_t want_positions,
                                   const dfa_tune *tune);
 

@@ -66,12 +66,12 @@ struct ScanParams {
     int64_t nwalks;
     unsigned long long *total;    // kCount: += matches
     uint32_t *walk_count;         // kCountPerWalk: matches per walk, written by waves with a match
-                                  // (read back by kPositions)
+                                  // (read back by kPositions); kCountPerWave: matches per wave
     uint16_t *walk_buf;           // kCountPerWalk: start offsets (within the walk) of its first kStaged matches
     uint16_t *walk_buf1;          //   and of the next kBuffered - kStaged
-    unsigned long long *wg_part;  // kCountPerWalk: matches per workgroup
-    uint32_t *wg_waves;           // kCountPerWalk: bit w set when wave w of the workgroup had a match
-                                  // (read back by kPositions)
+    unsigned long long *wg_part;  // kCountPerWalk, kCountPerWave: matches per workgroup
+    uint32_t *wg_waves;           // kCountPerWalk, kCountPerWave: bit w set when wave w of the
+                                  // workgroup had a match (read back by kPositions)
     int32_t stage;                // kCountPerWalk: stage records in LDS (plans for short patterns)
     uint32_t rec_lds;             // in the kernel: LDS address of the wave's staged records (or 0)
     const uint32_t *wg_flag;      // kPositions: nonzero for a workgroup with a walk past its buffer
@@ -146,7 +146,7 @@ __device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m
 
 // Walk 16 bytes: byte b of word w is byte jb + 4w + b of the walk.  GUARD:
 // only bytes below the walk's length count.  kCount: ballot + scalar count.
-// kCountPerWalk: per-walk count and the first kBuffered match ends (the
+// kCountPerWalk: per-walk count and the first kBuffered match starts (the
 // total is summed from the per-walk counts at the end).  kPositions: write
 // the start offset of every match.
 template <int K, int MODE, bool GUARD>
