@@ -597,7 +597,8 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
 // One block of kPartsThreads: sup[k] = exclusive prefix of the super-block
 // sums (nsup = ceil(nb / kSuper) of them); *count = the total.
 __global__ __launch_bounds__(kPartsThreads) void k_scan_parts(const unsigned long long *part, int64_t nb,
-                                                              unsigned long long *sup, int64_t *count) {
+                                                              unsigned long long *sup, int64_t *count,
+                                                              uint32_t *list_count) {
     __shared__ unsigned long long sh[kPartsThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int64_t nsup = (nb + kSuper - 1) / kSuper;
@@ -626,7 +627,10 @@ __global__ __launch_bounds__(kPartsThreads) void k_scan_parts(const unsigned lon
         sup[i] = run;
         run += x;
     }
-    if (threadIdx.x == 0) *count = int64_t(total);
+    if (threadIdx.x == 0) {
+        *count = int64_t(total);
+        if (list_count) *list_count = 0u;  // (per-wave plans) the placement pass appends to the list
+    }
 }
 
 // One block of kPlaceThreads per `per_block` consecutive counting workgroups
@@ -743,7 +747,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
 __global__ __launch_bounds__(kPlaceThreads) void k_place_waves(const uint32_t *wave_count,
                                                                const unsigned long long *part,
                                                                const unsigned long long *sup, int64_t nwaves,
-                                                               int wpg, int per_block, int64_t *wave_off) {
+                                                               int wpg, int per_block, int64_t *wave_off,
+                                                               uint32_t *list, uint32_t *list_count) {
     __shared__ unsigned long long sh[kPlaceThreads / kWave];
     const int t = threadIdx.x;
     const int64_t wg0 = int64_t(blockIdx.x) * per_block;
@@ -755,20 +760,24 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place_waves(const uint32_t *w
     const int64_t base = int64_t(sup[wg0 / kSuper] + block_sum(before, sh));
     unsigned long long total;
     const unsigned long long ex = block_exclusive_scan(c, sh, &total);
-    if (c) wave_off[w] = base + int64_t(ex);
+    if (c) {
+        wave_off[w] = base + int64_t(ex);
+        list[atomicAdd(list_count, 1u)] = uint32_t(w);  // any order: each wave knows its slot
+    }
 }
 
-// Positions of per-wave plans.  One workgroup of kRewalkThreads per counting
-// workgroup; it leaves at once unless one of its waves had a match.  Each
-// such wave's 64 spans (64 S bytes from the wave's first walk) are split over
-// the threads, each walking its share of S / 4 bytes plus the m - 1 bytes
-// after it twice from the start state: once counting the matches that start
-// in its share, once writing them from its output slot (the wave's slot plus
-// a block scan of the counts).  A lone wave walking its own 64 spans twice
-// would leave its result waiting on two serial walks of S + m - 1 bytes.
-// The table is read through a pointer into dynamic LDS (the block scan's
-// slots follow it there), the text with 4-byte loads.
-constexpr int kRewalkThreads = 256;
+// Positions of per-wave plans.  A fixed grid of kRewalkGroups workgroups of
+// kRewalkThreads goes through the list of waves with a match (written by the
+// placement pass; its length was set before the grid starts, so every loop
+// ends).  Each such wave's 64 spans (64 S bytes from the wave's first walk)
+// are split into shares of 64 S / kRewalkThreads bytes (rounded up to 16),
+// each walked with the m - 1 bytes after it twice from the start state: once
+// counting the matches that start in it, once writing them from its output
+// slot (the wave's slot plus a block scan of the counts).  The table is read
+// through a pointer into dynamic LDS (the block scan's slots follow it
+// there).
+constexpr int kRewalkThreads = 1024;
+constexpr int kRewalkGroups = 1024;
 
 // One thread's share: the matches starting in [a, b), walking bytes
 // [a, min(n, b + m - 1)) from the start state (a match ends m - 1 bytes after
@@ -817,11 +826,12 @@ __device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n,
 }
 
 __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, int64_t n, const uint8_t *table,
-                                                           int32_t m, int64_t S, int wpg, const uint32_t *wg_waves,
-                                                           const int64_t *wave_off, int64_t *positions, int64_t cap) {
+                                                           int32_t m, int64_t S, const uint32_t *list,
+                                                           const uint32_t *list_count, const int64_t *wave_off,
+                                                           int64_t *positions, int64_t cap) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t mask = wg_waves[blockIdx.x];
-    if (mask == 0) return;
+    const uint32_t nlist = *list_count;
+    if (blockIdx.x >= nlist) return;
     const int t = threadIdx.x;
     {
         const uint32_t *tg = reinterpret_cast<const uint32_t *>(table);
@@ -831,10 +841,10 @@ __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, 
     }
     unsigned long long *sh = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(m));
     __syncthreads();
-    const int64_t share = kWave * S / kRewalkThreads;  // S is a multiple of 16
-    for (int w = 0; w < wpg; ++w) {
-        if (((mask >> w) & 1u) == 0) continue;  // uniform over the workgroup
-        const int64_t gw = int64_t(blockIdx.x) * wpg + w;
+    int64_t share = (kWave * S / kRewalkThreads + 15) / 16 * 16;  // S is a multiple of 16
+    if (share < 16) share = 16;
+    for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {  // uniform over the workgroup
+        const int64_t gw = list[i];
         const int64_t start = gw * kWave * S;
         const int64_t end = start + kWave * S < n ? start + kWave * S : n;
         const int64_t a = start + t * share;
@@ -971,11 +981,12 @@ int64_t max_walks(int64_t n, const dfa_tune *t) { return n > 0 ? dfa::ceil_div(n
 
 // workspace layout: walk counts u32[nw] | walk offsets i64[nw] | workgroup
 // totals u64[nb] | super-block prefixes u64[nb / kSuper] | workgroup flags
-// u32[nb] | workgroup wave masks u32[nb] | first kStaged match starts
+// (per-wave plans: the list of waves with a match) u32[nb] | workgroup wave
+// masks u32[nb] | the list's length u32 | first kStaged match starts
 // u16[nw * kStaged] | the next ones u16[nw * kStaged], with nb sized for the
-// smallest workgroup (64 walks)
+// smallest workgroup (64 walks), i.e. the number of waves
 struct WsLayout {
-    int64_t cnt = 0, off = 0, part = 0, sup = 0, flag = 0, waves = 0, buf = 0, buf1 = 0, total = 0;
+    int64_t cnt = 0, off = 0, part = 0, sup = 0, flag = 0, waves = 0, ctr = 0, buf = 0, buf1 = 0, total = 0;
 };
 WsLayout ws_layout(int64_t nw) {
     WsLayout L;
@@ -987,7 +998,8 @@ WsLayout ws_layout(int64_t nw) {
     L.sup = L.part + dfa::round_up(nb * 8, 256);
     L.flag = L.sup + dfa::round_up(dfa::ceil_div(nb, kSuper) * 8, 256);
     L.waves = L.flag + dfa::round_up(nb * 4, 256);
-    L.buf = L.waves + dfa::round_up(nb * 4, 256);
+    L.ctr = L.waves + dfa::round_up(nb * 4, 256);
+    L.buf = L.ctr + 256;
     L.buf1 = L.buf + dfa::round_up(nw * 2 * kStaged, 256);
     L.total = L.buf1 + dfa::round_up(nw * 2 * (kBuffered - kStaged), 256);
     return L;
@@ -1190,6 +1202,7 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     unsigned long long *sup = reinterpret_cast<unsigned long long *>(ws + L.sup);
     uint32_t *flag = reinterpret_cast<uint32_t *>(ws + L.flag);
     uint32_t *waves = reinterpret_cast<uint32_t *>(ws + L.waves);
+    uint32_t *list_count = reinterpret_cast<uint32_t *>(ws + L.ctr);
     uint16_t *wbuf = reinterpret_cast<uint16_t *>(ws + L.buf);
     uint16_t *wbuf1 = reinterpret_cast<uint16_t *>(ws + L.buf1);
     if (group_walks > kMaxGroupWalks || pl.blocks > dfa::ceil_div(nw, kWave)) {
@@ -1206,17 +1219,19 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
         int rc = launch_walk(pl, kCountPerWave, sp, st);
         if (rc != DFA_OK) return rc;
         hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part,
-                           pl.blocks, sup, count);
+                           pl.blocks, sup, count, list_count);
         const int per_block = kPlaceThreads / pl.wpg;  // counting workgroups per placement block
         hipLaunchKernelGGL(k_place_waves, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0,
                            st, (const uint32_t *)wcnt, (const unsigned long long *)part,
-                           (const unsigned long long *)sup, dfa::ceil_div(nw, kWave), pl.wpg, per_block, woff);
+                           (const unsigned long long *)sup, dfa::ceil_div(nw, kWave), pl.wpg, per_block, woff, flag,
+                           list_count);
         if (!hip_ok(hipGetLastError(), "placement launch")) return DFA_EHIP;
         const int rw_lds = table_lds_bytes(m) + kRewalkThreads / kWave * 8;
         if (!dfa::allow_lds(reinterpret_cast<const void *>(&k_rewalk), table_lds_bytes(DFA_MAX_M) + 256))
             return DFA_EHIP;
-        hipLaunchKernelGGL(k_rewalk, dim3(unsigned(pl.blocks)), dim3(kRewalkThreads), rw_lds, st, text, n, table, m,
-                           pl.S, pl.wpg, (const uint32_t *)waves, (const int64_t *)woff, positions, cap);
+        hipLaunchKernelGGL(k_rewalk, dim3(unsigned(std::min<int64_t>(kRewalkGroups, dfa::ceil_div(nw, kWave)))),
+                           dim3(kRewalkThreads), rw_lds, st, text, n, table, m, pl.S, (const uint32_t *)flag,
+                           (const uint32_t *)list_count, (const int64_t *)woff, positions, cap);
         if (!hip_ok(hipGetLastError(), "k_rewalk launch")) return DFA_EHIP;
         dfa::clear_error();
         return DFA_OK;
@@ -1227,7 +1242,7 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     int rc = launch_walk(pl, kCountPerWalk, sp, st);
     if (rc != DFA_OK) return rc;
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kPartsThreads), 0, st, (const unsigned long long *)part, pl.blocks,
-                       sup, count);
+                       sup, count, nullptr);
     const int per_block = kPlaceWalks / group_walks;  // counting workgroups per placement block
     hipLaunchKernelGGL(k_place, dim3(unsigned(dfa::ceil_div(pl.blocks, per_block))), dim3(kPlaceThreads), 0, st,
                        (const uint32_t *)wcnt, (const uint16_t *)wbuf, (const uint16_t *)wbuf1,
