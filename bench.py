@@ -57,6 +57,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "text GB/s (and % of HBM peak) single-pattern; pattern-bytes/s batched; p50/p99"
+# LDS reads of 2 bytes the device can serve per second: 256 CUs x 2.4 GHz x 64 lanes
+LDS_PEAK_LOOKUPS = 256 * 2.4e9 * 64
 HBM_PEAK_GBS = 8000.0
 PATTERN_LENGTHS = (4, 8, 16, 32, 64)
 SCAN_SOURCES = [os.path.join(ROOT, "paper_1506_08612_amd", "csrc", f) for f in ("dfa_scan.hip", "walk_common.h")]
@@ -203,6 +205,12 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
             "ms": round(ms, 3), "one_per_launch_ms": round(base_ms, 3),
             "method": "merged multi-pattern automata (class-compressed 16-bit tables), HIP graph replay",
             "tune": entry["tune"], "automata": int(b.plan.nautomata), "states": int(b.plan.nstates),
+            # every automaton walks the whole text: two LDS reads per step (byte class, then the
+            # 16-bit transition), against 64 two-byte reads per clock per CU (128 B/clk LDS)
+            "lds_bound": {"steps_per_s": round(n * int(b.plan.nautomata) / (ms * 1e-3), 1),
+                          "lookups_per_s": round(2 * n * int(b.plan.nautomata) / (ms * 1e-3), 1),
+                          "peak_lookups_per_s": LDS_PEAK_LOOKUPS,
+                          "frac": round(2 * n * int(b.plan.nautomata) / (ms * 1e-3) / LDS_PEAK_LOOKUPS, 4)},
             "items": int(b.plan.nitems), "counts_equal_one_per_launch": equal,
             "separate_automata": {"ms": round(sep_ms, 3), "pattern_bytes_per_s": round(pb / (sep_ms * 1e-3), 1),
                                   "speedup_vs_one_per_launch": round(base_ms / sep_ms, 2),
@@ -227,11 +235,26 @@ def bench_degenerate(torch, api, d, n):
     g = graph.GraphedBatch(d, b)
     ms = _events_ms(torch, g.replay, 5)
     nk = int(b.batch.plan.npairs)
+    # the oracle's per-position check of the code sets, one thread per query, on a prefix
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    sn = min(n, 40_000_000)
+    sample = d[:sn].cpu().numpy()
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda q: oracle.degenerate_count(sample, q[1], q[2]), queries))
+    cpu_s = time.perf_counter() - t0
     return {"workload": f"{len(queries)} degenerate 8-mer queries (9 with a 3-way position), both strands, "
                         f"over the same {n} B text; {nk} plain k-mers after expansion",
             "ms": round(ms, 3), "text_GBps": round(n / ms / 1e6, 1),
+            "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
             "query_bytes_per_s": round(n * len(queries) / (ms * 1e-3), 1),
-            "counts": [int(x) for x in b.counts.cpu().numpy()[:len(queries)]]}
+            "counts": [int(x) for x in b.counts.cpu().numpy()[:len(queries)]],
+            "cpu_baseline": {"value": round(sn * len(queries) / cpu_s, 1), "unit": "query-bytes/s", "cores": cores,
+                             "kind": "oracle",
+                             "sample": f"first {sn} bytes, the {len(queries)} queries job-parallel over {cores} "
+                                       f"threads, {cpu_s:.1f} s on {cpu_model()}"}}
 
 
 def bench_study(torch, api, text, dtext, pats):
@@ -317,10 +340,20 @@ def bench_fasta(torch, api, text, dtext, reps=5):
     kept, nrec = (int(x) for x in tot.cpu().tolist())
     same = kept == text.size and bool(torch.equal(out[:kept], dtext))
     del draw, out, ws
+    # the oracle's line-by-line normaliser (plain Python), one thread, on a prefix
+    import oracle
+    sn = 16_000_000
+    t0 = time.perf_counter()
+    oracle.fasta.normalize(raw[:sn].tobytes())
+    cpu_s = time.perf_counter() - t0
+    # HBM bytes of the three passes: the text read twice, the kept bytes written once
     return {"workload": f"the {text.size} B genome as FASTA: {nrec} records, 60 bases per line, "
                         f"10% soft-masked; {n} B of FASTA text",
             "ms": round(ms, 3), "GBps": round(n / ms / 1e6, 1), "records": nrec,
-            "normalised_equals_source": same}
+            "hbm_frac": round((2 * n + kept) / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "normalised_equals_source": same,
+            "cpu_baseline": {"value": round(sn / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                             "sample": f"first {sn} bytes of the FASTA text, {cpu_s:.1f} s on {cpu_model()}"}}
 
 
 def bench_segmented(torch, api, synth):
