@@ -137,30 +137,33 @@ template <bool GUARD>
 __device__ __forceinline__ void mwalk16(const v4u &t, uint32_t &q, uint32_t jb, const MCtx &x, const MLane &L,
                                         unsigned char *smem, const MParams &p) {
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
-    // the byte classes of each half of the unit first: they do not depend on
-    // the state, so their reads are in flight together and only the
-    // transition read is left on the chain from one step to the next (8 at a
-    // time: 16 would cost 8 more registers, i.e. resident waves where the
-    // automata are small)
-    uint32_t k2[8];
+    // Per half of the unit: its 8 byte classes first (they do not depend on
+    // the state, so their reads are in flight together), then the 8 steps,
+    // which keep only the transition read on the state chain, then the
+    // visits of the states reached (their counter updates off the chain).
+    // Halves rather than the whole unit: 16 of each would cost 16 more
+    // registers, i.e. resident waves where the automata are small.
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        if (w % 2 == 0) {
+    for (int h = 0; h < 2; ++h) {
+        uint32_t k2[8], qs[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                k2[i] = *reinterpret_cast<lds_u16 *>(
-                    uintptr_t(x.cmap + 2u * ((t[w + i / 4] >> (8 * (i % 4))) & 0xffu)));
+        for (int i = 0; i < 8; ++i)
+            k2[i] = *reinterpret_cast<lds_u16 *>(
+                uintptr_t(x.cmap + 2u * ((t[2 * h + i / 4] >> (8 * (i % 4))) & 0xffu)));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2[i]));
+            if (GUARD && jb + uint32_t(8 * h + i) < L.lo) q = 0;  // in front of the segment: stay in the start state
+            qs[i] = q;
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t j = jb + uint32_t(4 * w + b);
-            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2[4 * (w % 2) + b]));
-            if (GUARD && j < L.lo) q = 0;  // in front of the segment: stay in the start state
-            if (q >= x.F) {
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t j = jb + uint32_t(8 * h + i);
+            if (qs[i] >= x.F) {
                 if (!GUARD || j < L.own)
-                    atomicAdd(hist + (q - x.F), 1u);
+                    atomicAdd(hist + (qs[i] - x.F), 1u);
                 else if (j < L.len)
-                    overlap_hit(p, x, q, j, L.own);
+                    overlap_hit(p, x, qs[i], j, L.own);
             }
         }
     }
