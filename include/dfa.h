@@ -302,7 +302,7 @@ int64_t dfa_degenerate_expand(const uint8_t *code, int32_t m, int32_t both_stran
 /* Device workspace for dfa_fasta_normalize on n bytes (0 for n == 0). */
 int64_t dfa_fasta_workspace_bytes(int64_t n);
 
-/* Device-only.  Turns FASTA text raw[0..n-1] (device, 4-byte aligned) into
+/* Device-only.  Turns FASTA text raw[0..n-1] (device, 16-byte aligned) into
  * plain sequence: a line whose first byte is '>' is a header (it starts a
  * record; none of its bytes are kept); every other byte is kept except '\n'
  * and '\r', with 'a'..'z' made upper case (soft-masking dropped).

@@ -9,28 +9,33 @@
 // starts where the kept bytes stood when its header was read.
 //
 // Whether a byte is kept depends on the first byte of its line, which may lie
-// far back, so the text is cut into 64 KiB chunks and processed in three
-// passes:
-//   A  per chunk: its last line start (with whether that line is a header),
+// far back, so the text is cut into 32 KiB units, one per wave, and processed
+// in three steps:
+//   A  per unit: its last line start (with whether that line is a header),
 //      its header count, and its kept bytes -- those before its first line
-//      start counted apart, as their line began in an earlier chunk;
-//   B  one workgroup: the line each chunk starts in (the last line start of
-//      all earlier chunks), hence its kept bytes, and the chunk's output and
-//      record offsets (prefix sums);
-//   C  per chunk again: the kept bytes written, compacted, at their offsets,
+//      start counted apart, as their line began in an earlier unit;
+//   B  the unit summaries combined in text order by an associative operator
+//      (one kernel for the totals of blocks of 2048 units, one for each
+//      block's prefix and its units' own): the line each unit starts in, its
+//      output offset and its first record index;
+//   C  per unit again: the kept bytes written, compacted, at their offsets,
 //      and the record starts.
-// A line start s is carried as 2 s + (byte s is '>'), so that one prefix max
-// over line starts gives both where the current line began and whether it is
-// a header, with no load of that byte.  Within a chunk a workgroup of 256
-// threads takes 4 KiB per round, 16 bytes per thread (four dword loads;
-// consecutive threads read consecutive 16-byte pieces, and the byte before a
-// wave's first piece comes with them); per round one block scan carries the
-// line start (prefix max) and one the kept and header counts (prefix sums,
-// packed in 64 bits).
+// A wave takes 1 KiB per round, 16 bytes per lane (one 16-byte load;
+// consecutive lanes read consecutive pieces), with the next two rounds'
+// loads in flight.  A line start s is held as 2 s + (byte s is '>'), relative
+// to the unit, so that one wave-wide prefix max per round gives every byte
+// both where its line began and whether that line is a header; in C one
+// wave-wide prefix sum gives the lanes' output offsets.  The scans are DPP
+// row shifts and row broadcasts, so the waves of a workgroup never wait for
+// each other.  C stages a round's kept bytes in a per-wave LDS ring indexed
+// by output address and stores whole aligned 16-byte blocks; the partial
+// blocks at a unit's two ends, shared with the neighbouring units, are
+// stored byte by byte.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 
 #include "dfa.h"
@@ -39,277 +44,444 @@
 
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kWaveSize = 64;
-constexpr int kPer = 16;                 // bytes per thread per round
-constexpr int kRound = kThreads * kPer;  // bytes per round
-constexpr int64_t kChunk = 64 * 1024;    // bytes per workgroup
-constexpr int kPlanThreads = 1024;
+constexpr int kWaves = 4;                       // waves (units) per workgroup in A and C
+constexpr int kThreads = kWaves * kWaveSize;
+constexpr int kPer = 16;                        // bytes per lane per round
+constexpr int kRound = kWaveSize * kPer;        // bytes per wave per round
+constexpr int64_t kUnit = 32 * 1024;            // bytes per wave
+constexpr int kRing = 4096;                     // LDS staging ring per wave in C
+constexpr int kPlanThreads = 256;
+constexpr int kPlanPer = 8;                     // units per thread in B
+constexpr int64_t kPlanUnits = int64_t(kPlanThreads) * kPlanPer;
+constexpr int32_t kNone = INT32_MIN;            // no line start seen
 
-struct ChunkSummary {
-    int64_t last_ls;     // last line start in the chunk, as 2 s + header, or -1
+static_assert(kUnit % kRound == 0, "a unit is whole rounds");
+static_assert(kRing >= 2 * kRound + 2 * kPer, "the ring holds a round and the unstored tail");
+
+struct UnitSummary {
+    int64_t last_ls;     // last line start in the unit, as 2 s + header, or -1
     uint32_t pre;        // bytes before its first line start that a sequence line would keep
     uint32_t kept;       // kept bytes from its first line start on
-    uint32_t headers;    // header lines starting in the chunk
+    uint32_t headers;    // header lines starting in the unit
     uint32_t pad;
 };
 
-struct ChunkPlan {
-    int64_t ls_before;   // last line start before the chunk (2 s + header), or -1
-    int64_t out_off;     // kept bytes before the chunk
-    int64_t rec_off;     // records before the chunk
+// A run of text summarised as a UnitSummary, with 64-bit counts.
+struct Agg {
+    int64_t ls;
+    unsigned long long pre, kept, hdr;
+};
+
+struct UnitPlan {
+    int64_t ls_before;   // last line start before the unit (2 s + header), or -1
+    int64_t out_off;     // kept bytes before the unit
+    int64_t rec_off;     // records before the unit
 };
 
 constexpr uint32_t kNl = '\n', kCr = '\r', kGt = '>';
 
-__device__ __forceinline__ int64_t wave_incl_max(int64_t v) {
-    const int lane = threadIdx.x & (kWaveSize - 1);
-#pragma unroll
-    for (int d = 1; d < kWaveSize; d <<= 1) {
-        const int64_t u = __shfl_up(v, d);
-        if (lane >= d) v = u > v ? u : v;
-    }
+// ---- wave-wide scans (DPP: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, wave_shr:1 = 0x138; lanes without a source keep `old`)
+
+constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143, kWaveShr1 = 0x138;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int32_t dpp_i32(int32_t old, int32_t v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// inclusive prefix max over the wave's 64 lanes (all lanes active)
+__device__ __forceinline__ int32_t wave_incl_max(int32_t v) {
+    v = max(v, dpp_i32<kRowShr + 1, 0xf>(kNone, v));
+    v = max(v, dpp_i32<kRowShr + 2, 0xf>(kNone, v));
+    v = max(v, dpp_i32<kRowShr + 4, 0xf>(kNone, v));
+    v = max(v, dpp_i32<kRowShr + 8, 0xf>(kNone, v));
+    v = max(v, dpp_i32<kBcast15, 0xa>(kNone, v));
+    v = max(v, dpp_i32<kBcast31, 0xc>(kNone, v));
     return v;
 }
 
-__device__ __forceinline__ unsigned long long wave_incl_sum(unsigned long long v) {
-    const int lane = threadIdx.x & (kWaveSize - 1);
-#pragma unroll
-    for (int d = 1; d < kWaveSize; d <<= 1) {
-        const unsigned long long u = __shfl_up(v, d);
-        if (lane >= d) v += u;
-    }
-    return v;
+// inclusive prefix sum over the wave's 64 lanes (all lanes active)
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    int32_t v = int32_t(x);
+    v += dpp_i32<kRowShr + 1, 0xf>(0, v);
+    v += dpp_i32<kRowShr + 2, 0xf>(0, v);
+    v += dpp_i32<kRowShr + 4, 0xf>(0, v);
+    v += dpp_i32<kRowShr + 8, 0xf>(0, v);
+    v += dpp_i32<kBcast15, 0xa>(0, v);
+    v += dpp_i32<kBcast31, 0xc>(0, v);
+    return uint32_t(v);
 }
 
-// exclusive prefix max over the block (any multiple of 64 threads up to
-// 1024), seeded with `carry`; *all = block max (and carry)
-__device__ __forceinline__ int64_t block_excl_max(int64_t v, int64_t carry, int64_t *sh, int64_t *all) {
-    const int lane = threadIdx.x & (kWaveSize - 1), w = threadIdx.x / kWaveSize;
-    const int nw = blockDim.x / kWaveSize;
-    const int64_t inc = wave_incl_max(v);
-    int64_t ex = __shfl_up(inc, 1);
-    if (lane == 0) ex = -1;
-    if (lane == kWaveSize - 1) sh[w] = inc;
-    __syncthreads();
-    int64_t before = carry, tot = carry;
-    for (int i = 0; i < nw; ++i) {
-        if (i < w) before = sh[i] > before ? sh[i] : before;
-        tot = sh[i] > tot ? sh[i] : tot;
-    }
-    __syncthreads();
-    *all = tot;
-    return ex > before ? ex : before;
+// v of the previous lane; lane 0 gets `first`
+__device__ __forceinline__ int32_t from_prev_lane(int32_t v, int32_t first) {
+    return dpp_i32<kWaveShr1, 0xf>(first, v);
 }
 
-// exclusive prefix sum over the block (any multiple of 64 threads up to 1024);
-// *all = block total
-__device__ __forceinline__ unsigned long long block_excl_sum(unsigned long long v, unsigned long long *sh,
-                                                             unsigned long long *all) {
-    const int lane = threadIdx.x & (kWaveSize - 1), w = threadIdx.x / kWaveSize;
-    const int nw = blockDim.x / kWaveSize;
-    const unsigned long long inc = wave_incl_sum(v);
-    if (lane == kWaveSize - 1) sh[w] = inc;
-    __syncthreads();
-    unsigned long long before = 0, tot = 0;
-    for (int i = 0; i < nw; ++i) {
-        if (i < w) before += sh[i];
-        tot += sh[i];
-    }
-    __syncthreads();
-    *all = tot;
-    return before + inc - v;
+__device__ __forceinline__ int32_t lane63(int32_t v) { return __builtin_amdgcn_readlane(v, 63); }
+
+// ---- one lane's 16 bytes of a round
+
+struct Piece {
+    uint32_t w[4];       // byte j is byte j % 4 of w[j / 4]
+    uint32_t valid;      // bit j: byte j lies below the end of the unit
+};
+
+// The 16 bytes at p, all present (raw + p is 16-byte aligned).
+__device__ __forceinline__ Piece load_full(const uint8_t *raw, int64_t p) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(raw + p);
+    Piece x;
+    x.w[0] = v.x;
+    x.w[1] = v.y;
+    x.w[2] = v.z;
+    x.w[3] = v.w;
+    x.valid = 0xffffu;
+    return x;
 }
 
-// The thread's kPer bytes of a round (positions p .. p+kPer-1; p is a multiple
-// of 4, raw 4-byte aligned), bytes at or past n absent (value 0x100), and
-// whether a line starts at each of them: at position 0, or after a '\n' (the
-// byte before the piece comes from the previous lane, or from memory for a
-// wave's first lane).
-__device__ __forceinline__ uint32_t load_piece(const uint8_t *raw, int64_t n, int64_t p, uint32_t (&b)[kPer]) {
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const uint32_t mem_before = lane == 0 ? (p == 0 ? kNl : (p - 1 < n ? uint32_t(raw[p - 1]) : 0x100u)) : 0u;
-    if (p + kPer <= n) {
+// Bytes p .. p+15 of the last, partial round of a unit: those at or past
+// `end` absent (read as '\n', not valid).
+__device__ __forceinline__ Piece load_tail(const uint8_t *raw, int64_t end, int64_t p) {
+    Piece x;
+    x.valid = 0;
 #pragma unroll
-        for (int q = 0; q < kPer / 4; ++q) {
-            const uint32_t w = *reinterpret_cast<const uint32_t *>(raw + p + 4 * q);
+    for (int q = 0; q < 4; ++q) x.w[q] = kNl * 0x01010101u;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[4 * q + j] = (w >> (8 * j)) & 0xffu;
+    for (int j = 0; j < kPer; ++j)
+        if (p + j < end) {
+            const int s = 8 * (j & 3);
+            x.w[j >> 2] = (x.w[j >> 2] & ~(0xffu << s)) | (uint32_t(raw[p + j]) << s);
+            x.valid |= 1u << j;
         }
-    } else {
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) b[j] = p + j < n ? raw[p + j] : 0x100u;
-    }
-    uint32_t before = uint32_t(__shfl_up(int(b[kPer - 1]), 1));
-    if (lane == 0) before = mem_before;
-    uint32_t starts = 0;  // bit j: a line starts at p + j
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const uint32_t prev = j ? b[j - 1] : before;
-        if (prev == kNl && b[j] <= 0xffu) starts |= 1u << j;
-    }
-    return starts;
+    return x;
 }
 
-// The last line start among the piece's bytes (2 s + header), or -1.
-__device__ __forceinline__ int64_t last_start(int64_t p, const uint32_t (&b)[kPer], uint32_t starts) {
-    if (!starts) return -1;
-    const int j = 31 - __clz(starts);
-    int64_t v = -1;
+__device__ __forceinline__ uint32_t byte_of(const Piece &x, int j) { return (x.w[j >> 2] >> (8 * (j & 3))) & 0xffu; }
+
+// bit j set iff byte j equals c
+__device__ __forceinline__ uint32_t eq_mask(const Piece &x, uint32_t c) {
+    uint32_t m = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-        if (k == j) v = 2 * (p + k) + (b[k] == kGt ? 1 : 0);
-    return v;
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t y = x.w[q] ^ (c * 0x01010101u);
+        // bit 7 of each byte: set iff the byte of y is zero
+        const uint32_t t = ~(((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y) & 0x80808080u;
+        m |= ((t >> 7 | t >> 14 | t >> 21 | t >> 28) & 0xfu) << (4 * q);
+    }
+    return m;
 }
 
-// Pass A
-__global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, int64_t n, ChunkSummary *sum) {
-    __shared__ int64_t shm[kThreads / kWaveSize];
-    __shared__ unsigned long long shs[kThreads / kWaveSize];
-    const int64_t c0 = int64_t(blockIdx.x) * kChunk;
-    const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    int64_t carry = -1;  // last line start inside the chunk so far
-    unsigned long long pre = 0, kept = 0, headers = 0;
-    for (int64_t r0 = c0; r0 < c1; r0 += kRound) {
-        const int64_t p = r0 + kPer * int64_t(threadIdx.x);
-        uint32_t b[kPer];
-        const uint32_t starts = load_piece(raw, c1, p, b);
-        int64_t all;
-        int64_t cur = block_excl_max(last_start(p, b, starts), carry, shm, &all);
-        carry = all;
-        // pre, kept and header counts of the thread, packed 21 bits apart (each < 2^21)
-        unsigned long long packed = 0;
+struct Lines {
+    uint32_t starts;     // bit j: a line starts at byte j
+    uint32_t hs;         // bit j: a header line starts at byte j
+    uint32_t elig;       // bit j: byte j is present and neither '\n' nor '\r'
+    uint32_t fill;       // bit j: the last line start at or before byte j in the piece is a header
+    uint32_t open;       // bit j: no line starts in the piece at or before byte j
+};
+
+// nl = eq_mask(x, '\n'); prev_nl = the byte before the piece is '\n' (or the
+// piece starts the text)
+__device__ __forceinline__ Lines analyse(const Piece &x, uint32_t nl, uint32_t prev_nl) {
+    Lines L;
+    L.starts = ((nl << 1) | prev_nl) & x.valid;
+    L.hs = L.starts & eq_mask(x, kGt);
+    L.elig = x.valid & ~(nl | eq_mask(x, kCr));
+    // copy each start's header flag forward to the bytes of its line
+    uint32_t v = L.hs, open = ~L.starts & 0xffffu;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const uint32_t x = b[j];
-            if (x > 0xffu) continue;
-            if ((starts >> j) & 1u) {
-                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
-                if (x == kGt) ++packed;
-            }
-            if (x == kNl || x == kCr) continue;
-            if (cur < 0)
-                packed += 1ull << 42;
-            else if (!(cur & 1))
-                packed += 1ull << 21;
+    for (int s = 1; s < kPer; s <<= 1) {
+        v |= (v << s) & open;
+        open &= (open << s) | ((1u << s) - 1u);
+    }
+    L.fill = v & 0xffffu;
+    L.open = open & 0xffffu;
+    return L;
+}
+
+// the piece's last line start (2 s + header, s relative to the unit), or kNone
+__device__ __forceinline__ int32_t last_start(const Lines &L, int32_t prel) {
+    if (!L.starts) return kNone;
+    const int j = 31 - __clz(L.starts);
+    return 2 * (prel + j) + int32_t((L.hs >> j) & 1u);
+}
+
+// Rounds of one unit, with the loads of the next two whole rounds in flight:
+// three pieces in fixed registers, each reloaded right after its round is
+// done, so that no piece is copied (a copy would wait for the load just
+// issued).  Every reload is issued, those past the unit's whole rounds from
+// its last whole piece again (a cache hit), so that the loads in flight are
+// the same on every path and each round waits for its own load only.  A last,
+// partial round (the end of the text) comes after them.
+template <class Step>
+__device__ __forceinline__ void unit_rounds(const uint8_t *raw, int64_t u0, int64_t u1, Step &&step) {
+    const int full = int((u1 - u0) / kRound);
+    const int64_t lp = int64_t(__lane_id()) * kPer;
+    if (full > 0) {
+        const auto at = [&](int r) { return u0 + int64_t(r < full ? r : full - 1) * kRound + lp; };
+        Piece a = load_full(raw, at(0)), b = load_full(raw, at(1)), c = load_full(raw, at(2));
+        for (int r = 0; r < full; r += 3) {
+            step(a, r);
+            a = load_full(raw, at(r + 3));
+            if (r + 1 < full) step(b, r + 1);
+            b = load_full(raw, at(r + 4));
+            if (r + 2 < full) step(c, r + 2);
+            c = load_full(raw, at(r + 5));
         }
-        unsigned long long t;
-        block_excl_sum(packed, shs, &t);
-        pre += t >> 42;
-        kept += (t >> 21) & 0x1fffffu;
-        headers += t & 0x1fffffu;
     }
-    if (threadIdx.x == 0) {
-        ChunkSummary s;
-        s.last_ls = carry;
-        s.pre = uint32_t(pre);
-        s.kept = uint32_t(kept);
-        s.headers = uint32_t(headers);
+    if (u0 + int64_t(full) * kRound < u1) step(load_tail(raw, u1, u0 + int64_t(full) * kRound + lp), full);
+}
+
+// Pass A: one wave per unit
+__global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, int64_t n, int64_t nunits,
+                                                            UnitSummary *sum) {
+    const int lane = __lane_id();
+    const int64_t u = int64_t(blockIdx.x) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    if (u >= nunits) return;
+    const int64_t u0 = u * kUnit, u1 = std::min(u0 + kUnit, n);
+    int32_t carry_nl = u0 == 0 ? 1 : int32_t(raw[u0 - 1] == kNl);
+    int32_t carry = kNone;
+    uint32_t pre = 0, kept = 0, hdr = 0;
+    unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
+        const uint32_t nl = eq_mask(x, kNl);
+        const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
+        const Lines L = analyse(x, nl, prev);
+        const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
+        const int32_t ex = max(from_prev_lane(incl, kNone), carry);
+        if (ex == kNone) {
+            pre += __popc(L.elig & L.open);
+            kept += __popc(L.elig & ~L.open & ~L.fill);
+        } else {
+            kept += __popc(L.elig & ~(L.fill | ((ex & 1) ? L.open : 0u)));
+        }
+        hdr += __popc(L.hs);
+        carry = max(carry, lane63(incl));
+        carry_nl = lane63(int32_t(nl >> 15)) & 1;
+    });
+    pre = uint32_t(lane63(int32_t(wave_incl_sum(pre))));
+    kept = uint32_t(lane63(int32_t(wave_incl_sum(kept))));
+    hdr = uint32_t(lane63(int32_t(wave_incl_sum(hdr))));
+    if (lane == 0) {
+        UnitSummary s;
+        s.last_ls = carry == kNone ? -1 : 2 * u0 + carry;
+        s.pre = pre;
+        s.kept = kept;
+        s.headers = hdr;
         s.pad = 0;
-        sum[blockIdx.x] = s;
+        sum[u] = s;
     }
 }
 
-// Pass B: one workgroup of kPlanThreads, each thread a run of consecutive
-// chunks: the last line start before each chunk (prefix max), then its kept
-// bytes and the output and record offsets (prefix sums).
-__global__ __launch_bounds__(kPlanThreads) void k_fasta_plan(const ChunkSummary *sum, int64_t nchunks,
-                                                             ChunkPlan *plan, int64_t *totals) {
-    __shared__ int64_t shm[kPlanThreads / kWaveSize];
-    __shared__ unsigned long long shs[kPlanThreads / kWaveSize];
-    const int64_t per = (nchunks + kPlanThreads - 1) / kPlanThreads;
-    const int64_t i0 = int64_t(threadIdx.x) * per, i1 = i0 + per < nchunks ? i0 + per : nchunks;
-    int64_t run_max = -1;
-    for (int64_t c = i0; c < i1; ++c) run_max = sum[c].last_ls > run_max ? sum[c].last_ls : run_max;
-    int64_t all;
-    const int64_t before0 = block_excl_max(run_max, -1, shm, &all);
-    // the kept bytes and records of the run
-    unsigned long long kept = 0, recs = 0;
-    int64_t before = before0;
-    for (int64_t c = i0; c < i1; ++c) {
-        const ChunkSummary s = sum[c];
-        kept += (before >= 0 && (before & 1) ? 0ull : s.pre) + s.kept;
-        recs += s.headers;
-        before = s.last_ls > before ? s.last_ls : before;
+// ---- pass B: ordered combination of unit summaries
+
+__device__ __forceinline__ Agg agg_identity() { return Agg{-1, 0ull, 0ull, 0ull}; }
+
+__device__ __forceinline__ Agg agg_of(const UnitSummary &s) { return Agg{s.last_ls, s.pre, s.kept, s.headers}; }
+
+// x followed by y
+__device__ __forceinline__ Agg combine(const Agg &x, const Agg &y) {
+    Agg r;
+    r.ls = y.ls >= 0 ? y.ls : x.ls;
+    r.hdr = x.hdr + y.hdr;
+    if (x.ls < 0) {  // y's leading bytes continue the line x's leading bytes are in
+        r.pre = x.pre + y.pre;
+        r.kept = x.kept + y.kept;
+    } else {         // they continue x's last line
+        r.pre = x.pre;
+        r.kept = x.kept + ((x.ls & 1) ? 0ull : y.pre) + y.kept;
     }
-    unsigned long long tk, tr;
-    unsigned long long out = block_excl_sum(kept, shs, &tk);
-    unsigned long long rec = block_excl_sum(recs, shs, &tr);
-    before = before0;
-    for (int64_t c = i0; c < i1; ++c) {
-        const ChunkSummary s = sum[c];
-        ChunkPlan cp;
-        cp.ls_before = before;
-        cp.out_off = int64_t(out);
-        cp.rec_off = int64_t(rec);
-        plan[c] = cp;
-        out += (before >= 0 && (before & 1) ? 0ull : s.pre) + s.kept;
-        rec += s.headers;
-        before = s.last_ls > before ? s.last_ls : before;
+    return r;
+}
+
+__device__ __forceinline__ Agg shfl_up_agg(const Agg &a, int d) {
+    Agg r;
+    r.ls = __shfl_up(a.ls, d);
+    r.pre = __shfl_up(a.pre, d);
+    r.kept = __shfl_up(a.kept, d);
+    r.hdr = __shfl_up(a.hdr, d);
+    return r;
+}
+
+// exclusive ordered scan over the block; *total = the whole block's
+__device__ Agg block_scan_excl(Agg v, Agg *sh, Agg *total) {
+    const int lane = threadIdx.x & (kWaveSize - 1), w = threadIdx.x / kWaveSize;
+    const int nw = blockDim.x / kWaveSize;
+    Agg inc = v;
+#pragma unroll
+    for (int d = 1; d < kWaveSize; d <<= 1) {
+        const Agg u = shfl_up_agg(inc, d);
+        if (lane >= d) inc = combine(u, inc);
     }
-    if (threadIdx.x == 0) {
-        totals[0] = int64_t(tk);
-        totals[1] = int64_t(tr);
+    Agg ex = shfl_up_agg(inc, 1);
+    if (lane == 0) ex = agg_identity();
+    if (lane == kWaveSize - 1) sh[w] = inc;
+    __syncthreads();
+    Agg before = agg_identity(), tot = agg_identity();
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) before = combine(before, sh[i]);
+        tot = combine(tot, sh[i]);
+    }
+    __syncthreads();
+    *total = tot;
+    return combine(before, ex);
+}
+
+// the thread's kPlanPer units of block `b`, combined
+__device__ __forceinline__ Agg thread_units(const UnitSummary *sum, int64_t nunits, int64_t b) {
+    const int64_t k0 = b * kPlanUnits + int64_t(threadIdx.x) * kPlanPer;
+    Agg a = agg_identity();
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i)
+        if (k0 + i < nunits) a = combine(a, agg_of(sum[k0 + i]));
+    return a;
+}
+
+// B1: the combined summary of each block of kPlanUnits units
+__global__ __launch_bounds__(kPlanThreads) void k_fasta_blocks(const UnitSummary *sum, int64_t nunits, Agg *blk) {
+    __shared__ Agg sh[kPlanThreads / kWaveSize];
+    Agg tot;
+    block_scan_excl(thread_units(sum, nunits, blockIdx.x), sh, &tot);
+    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+// B2: each block's prefix (the blocks before it), then its units' plans; the
+// last block writes the totals.  One block with no units writes zero totals.
+__global__ __launch_bounds__(kPlanThreads) void k_fasta_offsets(const UnitSummary *sum, int64_t nunits,
+                                                                const Agg *blk, int64_t nblk, UnitPlan *plan,
+                                                                int64_t *totals) {
+    __shared__ Agg sh[kPlanThreads / kWaveSize];
+    const int64_t b = blockIdx.x;
+    if (nunits == 0) {
+        if (threadIdx.x == 0) {
+            totals[0] = 0;
+            totals[1] = 0;
+        }
+        return;
+    }
+    // prefix over blocks 0 .. b-1, a contiguous run of them per thread
+    const int64_t per = (b + kPlanThreads - 1) / kPlanThreads;
+    Agg run = agg_identity();
+    for (int64_t i = int64_t(threadIdx.x) * per; i < std::min(b, int64_t(threadIdx.x + 1) * per); ++i)
+        run = combine(run, blk[i]);
+    Agg prefix;
+    block_scan_excl(run, sh, &prefix);
+    Agg tot;
+    const Agg ex = block_scan_excl(thread_units(sum, nunits, b), sh, &tot);
+    Agg cur = combine(prefix, ex);
+    const int64_t k0 = b * kPlanUnits + int64_t(threadIdx.x) * kPlanPer;
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) {
+        const int64_t k = k0 + i;
+        if (k >= nunits) break;
+        UnitPlan p;
+        p.ls_before = cur.ls;
+        p.out_off = int64_t(cur.kept + cur.pre);  // pre is 0: byte 0 starts a line
+        p.rec_off = int64_t(cur.hdr);
+        plan[k] = p;
+        cur = combine(cur, agg_of(sum[k]));
+    }
+    if (b == nblk - 1 && threadIdx.x == 0) {
+        const Agg all = combine(prefix, tot);
+        totals[0] = int64_t(all.kept + all.pre);
+        totals[1] = int64_t(all.hdr);
     }
 }
 
-// Pass C
-__global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, int64_t n, const ChunkPlan *plan,
-                                                          uint8_t *out, int64_t *rec_start, int64_t rec_cap) {
-    __shared__ int64_t shm[kThreads / kWaveSize];
-    __shared__ unsigned long long shs[kThreads / kWaveSize];
-    const int64_t c0 = int64_t(blockIdx.x) * kChunk;
-    const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
-    const ChunkPlan cp = plan[blockIdx.x];
-    int64_t carry = cp.ls_before;
-    int64_t o = cp.out_off;
-    int64_t rec = cp.rec_off;
-    for (int64_t r0 = c0; r0 < c1; r0 += kRound) {
-        const int64_t p = r0 + kPer * int64_t(threadIdx.x);
-        uint32_t b[kPer];
-        const uint32_t starts = load_piece(raw, c1, p, b);
-        int64_t all;
-        const int64_t cur0 = block_excl_max(last_start(p, b, starts), carry, shm, &all);
-        carry = all;
-        // kept bytes and header starts of the thread, packed as (kept << 32) | headers
-        int64_t cur = cur0;
-        unsigned long long packed = 0;
+// Pass C: one wave per unit
+__global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, int64_t n, int64_t nunits,
+                                                          const UnitPlan *plan, uint8_t *out, int64_t *rec_start,
+                                                          int64_t rec_cap) {
+    __shared__ __align__(16) uint8_t ring_all[kWaves][kRing];
+    const int lane = __lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    const int64_t u = int64_t(blockIdx.x) * kWaves + wv;
+    if (u >= nunits) return;
+    uint8_t *ring = ring_all[wv];
+    constexpr uint32_t kMask = kRing - 1;
+    const int64_t u0 = u * kUnit, u1 = std::min(u0 + kUnit, n);
+    const UnitPlan pl = plan[u];
+    int32_t carry_nl = u0 == 0 ? 1 : int32_t(raw[u0 - 1] == kNl);
+    // before any start in the unit: -1 if the open line is a header, else -2
+    int32_t carry = (pl.ls_before >= 0 && (pl.ls_before & 1)) ? -1 : -2;
+    int64_t o = pl.out_off, rec = pl.rec_off;
+    // output byte q sits at ring[(abase + q) & kMask]: ring blocks of 16 line up with out's
+    const uint32_t abase = uint32_t(reinterpret_cast<uintptr_t>(out));
+    const int64_t o_start = o;
+    const int64_t head_end = o_start + ((16u - ((abase + uint32_t(o_start)) & 15u)) & 15u);
+    int64_t f = o_start;  // output below f is stored
+    bool head_done = head_end == o_start;
+    unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
+        const uint32_t nl = eq_mask(x, kNl);
+        const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
+        const Lines L = analyse(x, nl, prev);
+        const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
+        const int32_t ex = max(from_prev_lane(incl, kNone), carry);
+        const uint32_t keep = L.elig & ~(L.fill | ((ex & 1) ? L.open : 0u));
+        // kept bytes and header starts of the lane, packed (each <= 16, wave sums <= 1024)
+        const uint32_t packed = uint32_t(__popc(keep)) | (uint32_t(__popc(L.hs)) << 16);
+        const uint32_t pin = wave_incl_sum(packed);
+        const uint32_t pex = pin - packed;
+        const uint32_t tot = uint32_t(lane63(int32_t(pin)));
+        // stage the kept bytes, upper-cased
+        uint32_t pos = abase + uint32_t(o) + (pex & 0xffffu);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const uint32_t x = b[j];
-            if (x > 0xffu) continue;
-            if ((starts >> j) & 1u) {
-                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
-                if (x == kGt) ++packed;
+            if ((keep >> j) & 1u) {
+                const uint32_t c = byte_of(x, j);
+                ring[pos & kMask] = uint8_t(c - 'a' < 26u ? c - 0x20u : c);
+                ++pos;
             }
-            if (x != kNl && x != kCr && !(cur & 1)) packed += 1ull << 32;
         }
-        unsigned long long tot;
-        const unsigned long long ex = block_excl_sum(packed, shs, &tot);
-        int64_t w = o + int64_t(ex >> 32);
-        int64_t h = rec + int64_t(ex & 0xffffffffu);
-        cur = cur0;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const uint32_t x = b[j];
-            if (x > 0xffu) continue;
-            if ((starts >> j) & 1u) {
-                cur = 2 * (p + j) + (x == kGt ? 1 : 0);
-                if (x == kGt) {
-                    if (h < rec_cap) rec_start[h] = w;
-                    ++h;
-                }
+        // record starts: the kept bytes before each header start
+        for (uint32_t hm = L.hs, k = 0; hm; hm &= hm - 1u, ++k) {
+            const int j = __builtin_ctz(hm);
+            const int64_t h = rec + int64_t(pex >> 16) + k;
+            if (h >= 0 && h < rec_cap) rec_start[h] = o + int64_t(pex & 0xffffu) + __popc(keep & ((1u << j) - 1u));
+        }
+        o += int64_t(tot & 0xffffu);
+        rec += int64_t(tot >> 16);
+        carry = max(carry, lane63(incl));
+        carry_nl = lane63(int32_t(nl >> 15)) & 1;
+        __builtin_amdgcn_wave_barrier();
+        // store: the head bytes once they are all staged, then whole 16-byte blocks
+        if (!head_done && o >= head_end) {
+            const int64_t q = o_start + lane;
+            if (q >= 0 && q < head_end && q < n) out[q] = ring[(abase + uint32_t(q)) & kMask];
+            f = head_end;
+            head_done = true;
+        }
+        if (head_done) {
+            const int64_t end = o - int64_t((abase + uint32_t(o)) & 15u);
+            for (int64_t k = lane; f + 16 * k < end; k += kWaveSize) {
+                const int64_t q = f + 16 * k;
+                const uint4 v = *reinterpret_cast<const uint4 *>(ring + ((abase + uint32_t(q)) & kMask));
+                if (q >= 0 && q + 16 <= n) *reinterpret_cast<uint4 *>(out + q) = v;
             }
-            if (x != kNl && x != kCr && !(cur & 1)) out[w++] = uint8_t(x - 'a' < 26u ? x - 0x20u : x);
+            f = std::max(f, end);
         }
-        o += int64_t(tot >> 32);
-        rec += int64_t(tot & 0xffffffffu);
-    }
+    });
+    // the unit's last partial block (or all of its output, if shorter than its head)
+    for (int64_t q = f + lane; q < o; q += kWaveSize)
+        if (q >= 0 && q < n) out[q] = ring[(abase + uint32_t(q)) & kMask];
 }
 
 using dfa::hip_ok;
 
-int64_t nchunks_of(int64_t n) { return n > 0 ? dfa::ceil_div(n, kChunk) : 0; }
+int64_t nunits_of(int64_t n) { return n > 0 ? dfa::ceil_div(n, kUnit) : 0; }
+
+struct Layout {
+    int64_t nunits, nblk, sum_bytes, blk_bytes, plan_bytes;
+};
+
+Layout layout_of(int64_t n) {
+    Layout l;
+    l.nunits = nunits_of(n);
+    l.nblk = dfa::ceil_div(l.nunits, kPlanUnits);
+    l.sum_bytes = dfa::round_up(l.nunits * int64_t(sizeof(UnitSummary)), 256);
+    l.blk_bytes = dfa::round_up(l.nblk * int64_t(sizeof(Agg)), 256);
+    l.plan_bytes = dfa::round_up(l.nunits * int64_t(sizeof(UnitPlan)), 256);
+    return l;
+}
 
 }  // namespace
 
@@ -318,8 +490,8 @@ extern "C" int64_t dfa_fasta_workspace_bytes(int64_t n) {
         dfa::set_error("dfa_fasta_workspace_bytes: n < 0");
         return DFA_EINVAL;
     }
-    const int64_t c = nchunks_of(n);
-    return dfa::round_up(c * int64_t(sizeof(ChunkSummary)), 256) + dfa::round_up(c * int64_t(sizeof(ChunkPlan)), 256);
+    const Layout l = layout_of(n);
+    return l.sum_bytes + l.blk_bytes + l.plan_bytes;
 }
 
 extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, int64_t *rec_start, int64_t rec_cap,
@@ -328,9 +500,9 @@ extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, 
         dfa::set_error("dfa_fasta_normalize: null argument or negative size");
         return DFA_EINVAL;
     }
-    if ((reinterpret_cast<uintptr_t>(raw) & 3) || (reinterpret_cast<uintptr_t>(totals) & 7) ||
+    if ((reinterpret_cast<uintptr_t>(raw) & 15) || (reinterpret_cast<uintptr_t>(totals) & 7) ||
         (reinterpret_cast<uintptr_t>(rec_start) & 7)) {
-        dfa::set_error("dfa_fasta_normalize: raw must be 4-byte, totals and rec_start 8-byte aligned");
+        dfa::set_error("dfa_fasta_normalize: raw must be 16-byte, totals and rec_start 8-byte aligned");
         return DFA_EINVAL;
     }
     const int64_t need = dfa_fasta_workspace_bytes(n);
@@ -339,20 +511,27 @@ extern "C" int dfa_fasta_normalize(const uint8_t *raw, int64_t n, uint8_t *out, 
                        (long long)workspace_bytes);
         return DFA_ENOSPACE;
     }
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int64_t c = nchunks_of(n);
-    if (c > 0x7fffffff) {
+    const Layout l = layout_of(n);
+    if (dfa::ceil_div(l.nunits, kWaves) > 0x7fffffff) {
         dfa::set_error("dfa_fasta_normalize: text too large");
         return DFA_EINVAL;
     }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = reinterpret_cast<uint8_t *>(workspace);
-    ChunkSummary *sum = reinterpret_cast<ChunkSummary *>(ws);
-    ChunkPlan *plan = reinterpret_cast<ChunkPlan *>(ws + dfa::round_up(c * int64_t(sizeof(ChunkSummary)), 256));
-    if (c > 0) hipLaunchKernelGGL(k_fasta_summary, dim3(unsigned(c)), dim3(kThreads), 0, st, raw, n, sum);
-    hipLaunchKernelGGL(k_fasta_plan, dim3(1), dim3(kPlanThreads), 0, st, (const ChunkSummary *)sum, c, plan, totals);
-    if (c > 0)
-        hipLaunchKernelGGL(k_fasta_write, dim3(unsigned(c)), dim3(kThreads), 0, st, raw, n, (const ChunkPlan *)plan,
-                           out, rec_start, rec_cap);
+    UnitSummary *sum = reinterpret_cast<UnitSummary *>(ws);
+    Agg *blk = reinterpret_cast<Agg *>(ws + l.sum_bytes);
+    UnitPlan *plan = reinterpret_cast<UnitPlan *>(ws + l.sum_bytes + l.blk_bytes);
+    const unsigned groups = unsigned(dfa::ceil_div(l.nunits, kWaves));
+    if (l.nunits > 0) {
+        hipLaunchKernelGGL(k_fasta_summary, dim3(groups), dim3(kThreads), 0, st, raw, n, l.nunits, sum);
+        hipLaunchKernelGGL(k_fasta_blocks, dim3(unsigned(l.nblk)), dim3(kPlanThreads), 0, st,
+                           (const UnitSummary *)sum, l.nunits, blk);
+    }
+    hipLaunchKernelGGL(k_fasta_offsets, dim3(unsigned(std::max<int64_t>(1, l.nblk))), dim3(kPlanThreads), 0, st,
+                       (const UnitSummary *)sum, l.nunits, (const Agg *)blk, l.nblk, plan, totals);
+    if (l.nunits > 0)
+        hipLaunchKernelGGL(k_fasta_write, dim3(groups), dim3(kThreads), 0, st, raw, n, l.nunits,
+                           (const UnitPlan *)plan, out, rec_start, rec_cap);
     if (!hip_ok(hipGetLastError(), "fasta launch")) return DFA_EHIP;
     dfa::clear_error();
     return DFA_OK;

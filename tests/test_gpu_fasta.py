@@ -1,7 +1,8 @@
 """GPU parity of FASTA normalisation (dfa_fasta_normalize) against the oracle's
 definition (oracle/fasta.py): kept bytes and record starts bit-exact, including
-headers and line breaks that straddle the kernel's 64 KiB chunks; then counts on
-the normalised records."""
+headers and line breaks that straddle the kernel's 32 KiB units (one per wave),
+its 1 KiB rounds and 16-byte lane pieces, outputs at every alignment, texts
+that span several blocks of the plan; then counts on the normalised records."""
 from __future__ import annotations
 
 import sys
@@ -21,7 +22,10 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 
 from paper_1506_08612_amd import api  # noqa: E402
 
-CHUNK = 64 * 1024
+UNIT = 32 * 1024      # bytes per wave
+ROUND = 1024          # bytes per wave and round
+PLAN_BLOCK = 2048     # units per block of the plan
+CHUNK = 2 * UNIT
 
 
 def say(*a):
@@ -44,10 +48,10 @@ def write_fasta(records, width, rng, crlf_frac=0.0, lower_frac=0.0):
     return bytes(out)
 
 
-def check(raw: bytes, rec_cap=1 << 16):
+def check(raw: bytes, rec_cap=1 << 16, want=None):
     d = api.to_device(np.frombuffer(raw, np.uint8).copy() if raw else np.zeros(0, np.uint8))
     seq, rec, kept, nrec = api.fasta_normalize(d, rec_cap)
-    want_seq, want_starts = ofasta.normalize(raw)
+    want_seq, want_starts = want if want is not None else ofasta.normalize(raw)
     assert kept == len(want_seq) and nrec == len(want_starts)
     assert bytes(seq.cpu().numpy().tobytes()) == want_seq
     assert rec.cpu().numpy().tolist() == want_starts[:rec_cap]
@@ -111,3 +115,72 @@ def test_counts_on_normalised_records():
     text = b"".join(s for _, s in recs)
     want = oracle.pair_counts(np.frombuffer(text, np.uint8), seg_off, pats, pair_seg, pair_pat)
     assert np.array_equal(got, want)
+
+
+def test_unit_round_and_piece_boundaries():
+    # newlines and header starts on both sides of every kind of border: the last
+    # byte of a lane's piece, of a round, of a unit; a header line that runs over
+    # several units; CRLF split over a unit border
+    rng = np.random.default_rng(21)
+    body = synth.iid_gc41(4 * UNIT, 3).tobytes()
+    raw = bytearray()
+    for border in (16, ROUND, UNIT, 2 * UNIT, 3 * UNIT):
+        for d in (-2, -1, 0, 1):
+            target = border * (1 + len(raw) // border) + d
+            raw += body[:max(0, target - len(raw) - 1)] + b"\n"
+            raw += b">h%d\n" % d if d % 2 else b"acgt\r\n"
+    raw += b">" + b"x" * (2 * UNIT + 77) + b"\r\n" + body[:UNIT - 3] + b"\r\n" + body[:100]
+    for cut in (0, 1, 15, 16, 17, ROUND - 1, ROUND + 1):
+        say("cut", cut, "bytes", len(raw) - cut)
+        check(bytes(raw[:len(raw) - cut]))
+    check(write_fasta([(b"r", body)], 61, rng, lower_frac=1.0))
+
+
+def test_output_alignments():
+    # the kept bytes go to out + k for every k: whole 16-byte blocks in the middle
+    # of a unit's output, bytes at its two ends
+    rng = np.random.default_rng(5)
+    recs = [(b"c%d" % k, synth.iid_gc41(int(rng.integers(0, 3 * UNIT)), 40 + k).tobytes()) for k in range(9)]
+    raw = write_fasta(recs, 60, rng, crlf_frac=0.5, lower_frac=0.5)
+    want_seq, want_starts = ofasta.normalize(raw)
+    n = len(raw)
+    d = api.to_device(np.frombuffer(raw, np.uint8).copy())
+    big = torch.full((n + 64,), 0xA5, dtype=torch.uint8, device=d.device)
+    rec = torch.empty(64, dtype=torch.int64, device=d.device)
+    tot = torch.zeros(2, dtype=torch.int64, device=d.device)
+    ws = torch.empty(max(256, api.lib.dfa_fasta_workspace_bytes(n)), dtype=torch.uint8, device=d.device)
+    for k in range(17):
+        say("output offset", k)
+        big.fill_(0xA5)
+        api._check(api.lib.dfa_fasta_normalize(d.data_ptr(), n, big.data_ptr() + k, rec.data_ptr(), 64,
+                                               tot.data_ptr(), ws.data_ptr(), ws.numel(), api._stream_handle(None)))
+        kept, nrec = (int(x) for x in tot.cpu().tolist())
+        host = big.cpu().numpy()
+        assert kept == len(want_seq) and nrec == len(want_starts)
+        assert host[k:k + kept].tobytes() == want_seq
+        assert (host[:k] == 0xA5).all() and (host[k + kept:] == 0xA5).all()   # nothing outside
+        assert rec.cpu().numpy()[:nrec].tolist() == want_starts
+
+
+def test_several_plan_blocks():
+    # more units than one block of the plan combines: 2.3 blocks
+    rng = np.random.default_rng(9)
+    n_target = int(2.3 * PLAN_BLOCK * UNIT) // 1000 * 1000
+    seq = synth.iid_gc41(n_target, 17)
+    lines = seq.reshape(-1, 1000)
+    width = lines.shape[1] + 1
+    raw = np.full((lines.shape[0], width), ord("\n"), np.uint8)
+    raw[:, :-1] = lines
+    flat = raw.reshape(-1)
+    # a header every ~4 MB, placed at line starts
+    heads = sorted(set(int(x) for x in rng.integers(0, lines.shape[0], size=40)) | {0})
+    parts, prev = [], 0
+    for i, h in enumerate(heads):
+        parts.append(flat[prev * width:h * width].tobytes())
+        parts.append(b">rec%d\n" % i)
+        prev = h
+    parts.append(flat[prev * width:].tobytes())
+    text = b"".join(parts)
+    say("bytes", len(text), "units", -(-len(text) // UNIT))
+    want_seq = seq.tobytes()
+    check(text, want=(want_seq, [h * 1000 for h in heads]))

@@ -108,6 +108,23 @@ def test_count_argument_checks_run_before_launch():
     assert L.dfa_count(fake, 1 << 20, fake, 8, fake, fake, 10, fake, 16, None, None) == api.DFA_ENOSPACE
 
 
+def test_fasta_argument_checks_run_before_launch():
+    fake = 1 << 20
+    L = api.lib
+    ws = L.dfa_fasta_workspace_bytes(1000)
+    assert ws > 0 and L.dfa_fasta_workspace_bytes(0) == 0
+    assert L.dfa_fasta_workspace_bytes(-1) == api.DFA_EINVAL
+    # raw must be 16-byte aligned (whole-piece loads); out may have any alignment
+    for off in (1, 4, 8):
+        assert L.dfa_fasta_normalize(fake + off, 1000, fake, fake, 4, fake, fake, ws, None) == api.DFA_EINVAL
+        assert "aligned" in api.last_error()
+    assert L.dfa_fasta_normalize(fake, 1000, fake, fake, 4, fake + 4, fake, ws, None) == api.DFA_EINVAL
+    assert L.dfa_fasta_normalize(fake, 1000, None, fake, 4, fake, fake, ws, None) == api.DFA_EINVAL
+    assert L.dfa_fasta_normalize(fake, 1000, fake, None, 4, fake, fake, ws, None) == api.DFA_EINVAL
+    assert L.dfa_fasta_normalize(fake, 1000, fake, fake, 4, fake, fake, ws - 1, None) == api.DFA_ENOSPACE
+    assert L.dfa_fasta_normalize(fake, 1000, fake, fake, 4, fake, fake + 16, ws, None) == api.DFA_ENOSPACE
+
+
 def test_workspace_bytes():
     assert api.count_workspace_bytes(1 << 30, 8, False) == 0
     a = api.count_workspace_bytes(1 << 30, 8, True)
