@@ -157,19 +157,36 @@ __device__ __forceinline__ Piece load_tail(const uint8_t *raw, int64_t end, int6
     return x;
 }
 
-__device__ __forceinline__ uint32_t byte_of(const Piece &x, int j) { return (x.w[j >> 2] >> (8 * (j & 3))) & 0xffu; }
 
-// bit j set iff byte j equals c
-__device__ __forceinline__ uint32_t eq_mask(const Piece &x, uint32_t c) {
-    uint32_t m = 0;
+// bit j set iff byte j differs from c.  Per dword: 0x80 in each byte that
+// differs (exact: the low seven bits are added without carrying into the next
+// byte), then one 4-way byte dot product with weights 1, 2, 4, 8 (or 16 .. 128)
+// gathers the four flags into bits of the result.
+__device__ __forceinline__ uint32_t ne_mask(const Piece &x, uint32_t c) {
+    const uint32_t cc = c * 0x01010101u;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint32_t y = x.w[q] ^ (c * 0x01010101u);
-        // bit 7 of each byte: set iff the byte of y is zero
-        const uint32_t t = ~(((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y) & 0x80808080u;
-        m |= ((t >> 7 | t >> 14 | t >> 21 | t >> 28) & 0xfu) << (4 * q);
+        const uint32_t y = x.w[q] ^ cc;
+        const uint32_t t = (((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y) & 0x80808080u;
+        const uint32_t wgt = (q & 1) ? 0x80402010u : 0x08040201u;
+        if (q < 2)
+            lo = __builtin_amdgcn_udot4(t, wgt, lo, false);
+        else
+            hi = __builtin_amdgcn_udot4(t, wgt, hi, false);
     }
-    return m;
+    return (lo >> 7) | (hi << 1);  // lo, hi = 0x80 x the masks of bytes 0..7, 8..15
+}
+
+// the 16 bytes with 'a'..'z' made upper case (four at a time; bytes >= 0x80
+// are left alone, and no byte carries into the next)
+__device__ __forceinline__ void upper_case(const Piece &x, uint32_t (&up)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t lo7 = x.w[q] & 0x7f7f7f7fu;
+        const uint32_t lower = (lo7 + 0x1f1f1f1fu) & ~(lo7 + 0x05050505u) & ~x.w[q] & 0x80808080u;
+        up[q] = x.w[q] - (lower >> 2);
+    }
 }
 
 struct Lines {
@@ -180,13 +197,13 @@ struct Lines {
     uint32_t open;       // bit j: no line starts in the piece at or before byte j
 };
 
-// nl = eq_mask(x, '\n'); prev_nl = the byte before the piece is '\n' (or the
-// piece starts the text)
+// nl: bit j set iff byte j is '\n'; prev_nl: the byte before the piece is
+// '\n' (or the piece starts the text)
 __device__ __forceinline__ Lines analyse(const Piece &x, uint32_t nl, uint32_t prev_nl) {
     Lines L;
     L.starts = ((nl << 1) | prev_nl) & x.valid;
-    L.hs = L.starts & eq_mask(x, kGt);
-    L.elig = x.valid & ~(nl | eq_mask(x, kCr));
+    L.hs = L.starts & ~ne_mask(x, kGt);
+    L.elig = x.valid & ~nl & ne_mask(x, kCr);
     // copy each start's header flag forward to the bytes of its line
     uint32_t v = L.hs, open = ~L.starts & 0xffffu;
 #pragma unroll
@@ -243,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
     int32_t carry = kNone;
     uint32_t pre = 0, kept = 0, hdr = 0;
     unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
-        const uint32_t nl = eq_mask(x, kNl);
+        const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
         const Lines L = analyse(x, nl, prev);
         const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
@@ -411,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
     int64_t f = o_start;  // output below f is stored
     bool head_done = head_end == o_start;
     unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
-        const uint32_t nl = eq_mask(x, kNl);
+        const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
         const Lines L = analyse(x, nl, prev);
         const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
@@ -423,12 +440,13 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
         const uint32_t pex = pin - packed;
         const uint32_t tot = uint32_t(lane63(int32_t(pin)));
         // stage the kept bytes, upper-cased
+        uint32_t up[4];
+        upper_case(x, up);
         uint32_t pos = abase + uint32_t(o) + (pex & 0xffffu);
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             if ((keep >> j) & 1u) {
-                const uint32_t c = byte_of(x, j);
-                ring[pos & kMask] = uint8_t(c - 'a' < 26u ? c - 0x20u : c);
+                ring[pos & kMask] = uint8_t(up[j >> 2] >> (8 * (j & 3)));
                 ++pos;
             }
         }
