@@ -775,9 +775,12 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place_waves(const uint32_t *w
 // counting the matches that start in it, once writing them from its output
 // slot (the wave's slot plus a block scan of the counts).  The table is read
 // through a pointer into dynamic LDS (the block scan's slots follow it
-// there).
+// there).  256 groups (one per CU) cost less to launch than 1024 when the
+// list is short (a few microseconds per call) and measured the same on a
+// dense list (160 million matches, every N-run wave listed); 64 were twice
+// as slow there.
 constexpr int kRewalkThreads = 1024;
-constexpr int kRewalkGroups = 1024;
+constexpr int kRewalkGroups = 256;
 
 // One thread's share: the matches starting in [a, b), walking bytes
 // [a, min(n, b + m - 1)) from the start state (a match ends m - 1 bytes after
