@@ -157,7 +157,6 @@ __device__ __forceinline__ Piece load_tail(const uint8_t *raw, int64_t end, int6
     return x;
 }
 
-
 // bit j set iff byte j differs from c.  Per dword: 0x80 in each byte that
 // differs (exact: the low seven bits are added without carrying into the next
 // byte), then one 4-way byte dot product with weights 1, 2, 4, 8 (or 16 .. 128)

@@ -25,7 +25,7 @@ from paper_1506_08612_amd import api  # noqa: E402
 UNIT = 32 * 1024      # bytes per wave
 ROUND = 1024          # bytes per wave and round
 PLAN_BLOCK = 2048     # units per block of the plan
-CHUNK = 2 * UNIT
+TWO = 2 * UNIT        # two units: every multiple of it is a unit border too
 
 
 def say(*a):
@@ -71,17 +71,17 @@ def test_random_genomes(seed):
         check(raw)
 
 
-def test_chunk_boundary_cases():
-    # a header that starts exactly at a chunk start, one that straddles it, a newline as a
-    # chunk's last byte, a header longer than a chunk, no final newline, a preamble
-    body = b"ACGT" * (CHUNK // 4)
+def test_unit_border_cases():
+    # a header that starts exactly at a unit border, one that straddles one, a newline as a
+    # unit's last byte, a header longer than two units, no final newline, a preamble
+    body = b"ACGT" * (TWO // 4)
     raw = bytearray(b"acgtn\n")                       # preamble before the first header
-    raw += body[:CHUNK - len(raw) - 1] + b"\n"          # this newline is the chunk's last byte
-    raw += b">at_chunk_start\n" + body[:1000] + b"\n"
-    pad = 2 * CHUNK - len(raw) - 3
+    raw += body[:TWO - len(raw) - 1] + b"\n"            # this newline is a unit's last byte
+    raw += b">at_unit_start\n" + body[:1000] + b"\n"
+    pad = 2 * TWO - len(raw) - 3
     raw += body[:pad] + b"\n>s"                        # header straddling the second boundary
     raw += b"traddle header\n" + body[:5000] + b"\n"
-    raw += b">" + b"H" * (CHUNK + 123) + b"\n"          # header longer than a chunk
+    raw += b">" + b"H" * (TWO + 123) + b"\n"            # header longer than two units
     raw += body[:777] + b"\r\n>last\nAcGt"              # no final newline
     check(bytes(raw))
 
