@@ -174,6 +174,25 @@ def _torch():
     return torch
 
 
+def _ptr(t, dtype: str, name: str, min_numel: int = 0):
+    """Device address of tensor `t` for the library, after checking what the
+    library cannot: that it is a contiguous device tensor of `dtype` with at
+    least `min_numel` elements (the library reads and writes whole ranges from
+    the address it is given).  None for an empty tensor."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a device tensor, got one on {t.device}")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name}: needs at least {min_numel} elements, has {t.numel()}")
+    return t.data_ptr() if t.numel() else None
+
+
 def _stream_handle(stream) -> int:
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -202,12 +221,14 @@ def count_async(text, table, m: int, count_out, positions_out=None, cap: int = 0
                 workspace=None, t: Optional[Tune] = None, stream=None) -> None:
     """Enqueue dfa_count on the stream.  All tensors are device tensors:
     text uint8[n], table uint8[(m+1)*256], count_out int64[1], positions_out int64[cap]."""
+    txt = _ptr(text, "uint8", "text")
     n = text.numel()
-    wsp = workspace.data_ptr() if workspace is not None else None
-    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
-    pos = positions_out.data_ptr() if positions_out is not None else None
-    _check(lib.dfa_count(text.data_ptr() if n else None, n, table.data_ptr(), m, count_out.data_ptr(),
-                         pos, int(cap), wsp, wsb, _tune_ptr(t), _stream_handle(stream)))
+    tab = _ptr(table, "uint8", "table", (int(m) + 1) * ALPHABET if 1 <= m <= MAX_M else 0)
+    cnt = _ptr(count_out, "int64", "count_out", 1)
+    pos = _ptr(positions_out, "int64", "positions_out", int(cap)) if positions_out is not None else None
+    wsp = _ptr(workspace, "uint8", "workspace") if workspace is not None else None
+    wsb = workspace.numel() if workspace is not None else 0
+    _check(lib.dfa_count(txt, n, tab, m, cnt, pos, int(cap), wsp, wsb, _tune_ptr(t), _stream_handle(stream)))
 
 
 def count(text, table, m: int, t: Optional[Tune] = None, stream=None) -> int:
@@ -243,7 +264,8 @@ def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_c
     torch = _torch()
     out = torch.empty(1, dtype=torch.int64, device=text.device)
     times = torch.zeros(3 * wg_cap, dtype=torch.int64, device=text.device)
-    nb = _check(lib.dfa_count_timed(text.data_ptr(), text.numel(), table.data_ptr(), m, out.data_ptr(),
+    tab = _ptr(table, "uint8", "table", (int(m) + 1) * ALPHABET if 1 <= m <= MAX_M else 0)
+    nb = _check(lib.dfa_count_timed(_ptr(text, "uint8", "text"), text.numel(), tab, m, out.data_ptr(),
                                     times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
     k = min(nb, wg_cap)
     return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
@@ -325,7 +347,7 @@ class Batch:
 
     def run(self, text, stream=None):
         """Enqueue the scan; counts land in self.counts (device int64)."""
-        _check(lib.dfa_batch_run(text.data_ptr() if text.numel() else None, text.numel(),
+        _check(lib.dfa_batch_run(_ptr(text, "uint8", "text"), text.numel(),
                                  self.pset.tables.data_ptr(), self.pset.tables.numel(),
                                  self.workspace.data_ptr(),
                                  ctypes.byref(self.plan), self.counts.data_ptr(), _stream_handle(stream)))
@@ -421,7 +443,7 @@ class MergedBatch:
 
     def run(self, text, stream=None):
         """Enqueue the scan; counts land in self.counts (device int64)."""
-        _check(lib.dfa_merged_run(text.data_ptr() if text.numel() else None, text.numel(),
+        _check(lib.dfa_merged_run(_ptr(text, "uint8", "text"), text.numel(),
                                   self.workspace.data_ptr(), ctypes.byref(self.plan), self.counts.data_ptr(),
                                   _stream_handle(stream)))
         return self.counts[:self.ncounts]
@@ -490,6 +512,7 @@ def fasta_normalize(raw, rec_cap: int = 1 << 16, stream=None):
     (uint8 view of the kept bytes, int64 starts of the first min(records, rec_cap)
     records) and the exact (kept bytes, records) on the host (synchronises)."""
     torch = _torch()
+    src = _ptr(raw, "uint8", "raw")
     n = raw.numel()
     dev = raw.device
     out = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
@@ -497,7 +520,7 @@ def fasta_normalize(raw, rec_cap: int = 1 << 16, stream=None):
     tot = torch.zeros(2, dtype=torch.int64, device=dev)
     wsb = _check(lib.dfa_fasta_workspace_bytes(n))
     ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=dev)
-    _check(lib.dfa_fasta_normalize(raw.data_ptr() if n else None, n, out.data_ptr(), rec.data_ptr(), rec_cap,
+    _check(lib.dfa_fasta_normalize(src, n, out.data_ptr(), rec.data_ptr(), rec_cap,
                                    tot.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
     kept, nrec = (int(x) for x in tot.cpu().tolist())
     return out[:kept], rec[:min(nrec, rec_cap)], kept, nrec

@@ -181,3 +181,24 @@ def test_paper_scale_genome():
         assert off in set(pos[max(0, np.searchsorted(pos, off) - 1):np.searchsorted(pos, off) + 1].tolist())
     del d
     torch.cuda.empty_cache()
+
+
+def test_binding_rejects_bad_tensors():
+    # argument checks of the binding: no kernel is launched for any of these
+    d = api.to_device(np.frombuffer(b"ACGT" * 64, np.uint8).copy())
+    tab, m = api.device_table(b"ACGT")
+    out = torch.zeros(1, dtype=torch.int64, device=d.device)
+    pos = torch.zeros(8, dtype=torch.int64, device=d.device)
+    with pytest.raises(ValueError, match="dtype"):
+        api.count_async(d.view(torch.int8), tab, m, out)
+    with pytest.raises(ValueError, match="contiguous"):
+        api.count_async(d[::2], tab, m, out)
+    with pytest.raises(ValueError, match="at least"):
+        api.count_async(d, tab[:100], m, out)
+    with pytest.raises(ValueError, match="dtype"):
+        api.count_async(d, tab, m, out.view(torch.float64))
+    with pytest.raises(ValueError, match="at least"):
+        api.count_async(d, tab, m, out, pos, 9)
+    with pytest.raises(ValueError, match="contiguous"):
+        api.fasta_normalize(d[::2])
+    assert api.count(d, tab, m) == 64  # the same tensors, well formed

@@ -125,6 +125,18 @@ def test_fasta_argument_checks_run_before_launch():
     assert L.dfa_fasta_normalize(fake, 1000, fake, fake, 4, fake, fake + 16, ws, None) == api.DFA_ENOSPACE
 
 
+def test_binding_rejects_host_tensors_before_any_call():
+    import torch
+    tab = torch.zeros(9 * 256, dtype=torch.uint8)
+    out = torch.zeros(1, dtype=torch.int64)
+    with pytest.raises(ValueError, match="device tensor"):
+        api.count_async(torch.zeros(100, dtype=torch.uint8), tab, 8, out)
+    with pytest.raises(TypeError, match="torch tensor"):
+        api.count_async(np.zeros(100, np.uint8), tab, 8, out)
+    with pytest.raises(ValueError, match="device tensor"):
+        api.fasta_normalize(torch.zeros(100, dtype=torch.uint8))
+
+
 def test_workspace_bytes():
     assert api.count_workspace_bytes(1 << 30, 8, False) == 0
     a = api.count_workspace_bytes(1 << 30, 8, True)
