@@ -318,11 +318,34 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
         const uint32_t off_last = lane_off - 16u * lane_unit + 16u * (lane_unit < ulast ? lane_unit : ulast - 1);
         const uint32_t off_none = 16u * lane_unit;
         const int64_t wb = g0 * p.S;
+        const int hu = (p.m - 1 + 15) / 16;  // overlap units
+        v4u halo[K][H];
+        if (LINE == 64 && (p.S & 127) == 0) {
+            // Spans of whole 128-byte lines (every default span): rounds r
+            // and r + 1 arrive together as whole lines (fetch_pair), half the
+            // lanes holding each, and are staged one after the other.  The
+            // order of fetches, stages and walks is the one below for 64-byte
+            // rounds; R is even and at least 2.
+            v4u pp[K][8];
+            const uint32_t pair_off = uint32_t(lane / 8) * uint32_t(p.S) + 16u * uint32_t(lane % 8);
+            fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, 0, rlast);
+            stage_pair<K, 0>(pp, xb, lane);
+            grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, G::U);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, LINE, acc, wl, p);
+            stage_pair<K, 1>(pp, xb, lane);
+            fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, 2, rlast);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), LINE, acc, wl, p);
+            for (int r = 2; r < R; r += 2) {
+                stage_pair<K, 0>(pp, xb, lane);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
+                stage_pair<K, 1>(pp, xb, lane);
+                fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, r + 2, rlast);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE), LINE, acc, wl, p);
+            }
+        } else {
         v4u pa[K][G::U], pb[K][G::U];
         fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
         fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
-        const int hu = (p.m - 1 + 15) / 16;  // overlap units
-        v4u halo[K][H];
         // round 0 (and 1), then the steady state from round 2
         stage_round<K, LINE>(pa, xb, lane);
         grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
@@ -348,6 +371,7 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
             fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
             walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
                                              r + 1 == rlast ? lastlen : LINE, acc, wl, p);
+        }
         }
         // the overlap, from registers, then (m > 65) the rest of it from memory
         const uint32_t hb = uint32_t(p.S);

@@ -390,6 +390,52 @@ __device__ __forceinline__ void grab_halo(v4u (&h)[K][H], const v4u *xb, int lan
     }
 }
 
+// Rounds r and r + 1 (r even) of 64-byte rounds, fetched as whole 128-byte
+// lines (the walk's span is a multiple of 128 bytes and starts on a line):
+// load i of slot s covers walks 64 s + 8 i + lane / 8, bytes 16 (lane % 8)
+// .. + 15 of their line at 64 r, so lanes with lane % 8 < 4 hold round r and
+// the others round r + 1 (unit lane % 4 of it).  Non-temporal loads: the text
+// is read once, and whole-line non-temporal requests streamed faster than
+// plain ones on gfx950 (half-line ones slower: the second half of the line
+// then missed the cache).  Past the last round (r > rlast) the pair reads the
+// text's first line instead (a cache hit whose values are never used).
+// `pair_off` is (lane / 8) S + 16 (lane % 8).
+template <int K>
+__device__ __forceinline__ void fetch_pair(v4u (&pp)[K][8], const uint8_t *text, int64_t wb, int64_t S,
+                                           uint32_t pair_off, int lane, int r, int rlast) {
+    const bool real = r <= rlast;  // wave-uniform
+    const uint32_t off = real ? pair_off : 16u * uint32_t(lane % 8);
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t ub = real ? wb + int64_t(s * kWave + 8 * i) * S + int64_t(r) * 64 : 0;
+            pp[s][i] = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(text + ub + off));
+        }
+    }
+}
+
+// Round r (HALF 0) or r + 1 (HALF 1) of a fetched pair into the wave's
+// buffer: the same rows and units as stage_round<K, 64>, written by the half
+// of the lanes that holds that round.
+template <int K, int HALF>
+__device__ __forceinline__ void stage_pair(const v4u (&pp)[K][8], v4u *xb, int lane) {
+    using G = Geo<64>;
+    wave_lds_sync();  // the previous round's reads of this buffer are done
+    if ((lane % 8) / 4 == HALF) {
+        const int unit = lane % 4;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int row = 8 * i + lane / 8;
+                xb[(s * kWave + row) * G::U + (unit ^ G::swz(row))] = pp[s][i];
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
 // Round r of the wave's walks (in-bounds path): rounds before the last use the
 // lane's own unit offset, the last one the clamped offset; r past the last
 // round loads the text's first line (a cache hit whose values are never used).
