@@ -941,10 +941,10 @@ size_t scan_lds_bytes(int wpg, int K, int line, int m, int mode) {
     return size_t(wpg) * (K * kWave * line + (rec ? kRecBytes : 0)) + size_t(table_lds_bytes(m));
 }
 
-// Default span of one walk: 8 m rounded up to whole lines, at least 512 and
-// at most 2048 bytes.  Short walks make short workgroups, which the hardware
-// dispatcher balances well (the launch's tail, while the last workgroups
-// finish, shrinks with them); the span stays long against m so that the
+// Default span of one walk, in whole 128-byte lines: 512 bytes up to m = 16,
+// 1024 up to m = 64, 2048 beyond.  Short walks make short workgroups, which
+// the hardware dispatcher balances well (the launch's tail, while the last
+// workgroups finish, shrinks with them); the span grows with m so that the
 // overlap (m - 1 bytes walked twice) stays small.
 constexpr int64_t kSpanMin = 512;
 constexpr int64_t kSpanMax = 2048;
@@ -1087,8 +1087,10 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
         // loads cover exactly one cache line per walk.  A span that is not a
         // multiple of the line makes every round straddle two lines; with
         // hundreds of streaming waves per XCD the shared line is evicted from
-        // L2 before the next round needs it, and HBM reads double.
-        pl.S = std::min<int64_t>(kSpanMax, std::max<int64_t>(kSpanMin, dfa::round_up(int64_t(8) * m, 128)));
+        // L2 before the next round needs it, and HBM reads double.  Longer
+        // patterns take longer spans (m = 32 and 64 measured faster at 1024
+        // than at 512 bytes, shorter ones slower).
+        pl.S = m <= 16 ? kSpanMin : (m <= 64 ? 2 * kSpanMin : kSpanMax);
     }
     pl.rounds = int(dfa::ceil_div(pl.S + m - 1, pl.line));
     pl.nwalks = n > 0 ? dfa::ceil_div(n, pl.S) : 0;
