@@ -184,3 +184,27 @@ def test_several_plan_blocks():
     say("bytes", len(text), "units", -(-len(text) // UNIT))
     want_seq = seq.tobytes()
     check(text, want=(want_seq, [h * 1000 for h in heads]))
+
+
+def test_genome_scale_round_trip():
+    # the benchmark's FASTA workload at full size and in the launch it times: the 3.2 GB
+    # genome-like text written as FASTA (24 records, 60 bases per line, 10 % soft-masked in
+    # runs) normalises back to the text itself, with each record starting where the writer cut
+    # the text; the first 4 MB of the FASTA are also checked against the oracle directly
+    import bench
+    n = 3_200_000_000
+    text = synth.genome_like(n, 2, 0.05, 50_000)
+    raw = bench.fasta_bytes(text)
+    say("fasta bytes", raw.size)
+    d = api.to_device(raw)
+    seq, rec, kept, nrec = api.fasta_normalize(d, 64)
+    del d
+    assert kept == n and nrec == 24
+    cuts = np.linspace(0, n, 25).astype(np.int64)[:-1]
+    assert rec.cpu().numpy().tolist() == cuts.tolist()
+    dtext = api.to_device(text)
+    assert bool(torch.equal(seq, dtext))
+    del dtext
+    head = raw[:4_000_000].tobytes()
+    want, _ = ofasta.normalize(head[:head.rfind(b"\n") + 1])
+    assert seq[:len(want)].cpu().numpy().tobytes() == want
