@@ -323,9 +323,9 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
         if (LINE == 64 && (p.S & 127) == 0) {
             // Spans of whole 128-byte lines (every default span): rounds r
             // and r + 1 arrive together as whole lines (fetch_pair), half the
-            // lanes holding each, and are staged one after the other.  The
-            // order of fetches, stages and walks is the one below for 64-byte
-            // rounds; R is even and at least 2.
+            // lanes holding each, and are staged one after the other.  Fetches,
+            // stages and walks come in the same order as in the other branch
+            // with 64-byte rounds; here R is even and at least 2.
             v4u pp[K][8];
             const uint32_t pair_off = uint32_t(lane / 8) * uint32_t(p.S) + 16u * uint32_t(lane % 8);
             fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, 0, rlast);
@@ -343,35 +343,35 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
                 walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE), LINE, acc, wl, p);
             }
         } else {
-        v4u pa[K][G::U], pb[K][G::U];
-        fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
-        fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
-        // round 0 (and 1), then the steady state from round 2
-        stage_round<K, LINE>(pa, xb, lane);
-        grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
-        if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
-        walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
-        if (rlast >= 1) {
-            stage_round<K, LINE>(pb, xb, lane);
-            if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
-            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
-                                             p);
-        }
-        for (int r = 2; r < R; r += 2) {
+            v4u pa[K][G::U], pb[K][G::U];
+            fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 0, rlast);
+            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 1, rlast);
+            // round 0 (and 1), then the steady state from round 2
             stage_round<K, LINE>(pa, xb, lane);
-            if (LINE == 128)
-                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
-                                             acc, wl, p);
-            if (r + 1 > rlast) break;
-            stage_round<K, LINE>(pb, xb, lane);
-            if (LINE == 64)
-                fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
-            fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
-                                             r + 1 == rlast ? lastlen : LINE, acc, wl, p);
-        }
+            grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
+            if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
+            if (rlast >= 1) {
+                stage_round<K, LINE>(pb, xb, lane);
+                if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
+                fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
+                                                 p);
+            }
+            for (int r = 2; r < R; r += 2) {
+                stage_round<K, LINE>(pa, xb, lane);
+                if (LINE == 128)
+                    fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
+                                                 acc, wl, p);
+                if (r + 1 > rlast) break;
+                stage_round<K, LINE>(pb, xb, lane);
+                if (LINE == 64)
+                    fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
+                fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
+                                                 r + 1 == rlast ? lastlen : LINE, acc, wl, p);
+            }
         }
         // the overlap, from registers, then (m > 65) the rest of it from memory
         const uint32_t hb = uint32_t(p.S);
