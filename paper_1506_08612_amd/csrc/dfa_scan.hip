@@ -795,9 +795,12 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place_waves(const uint32_t *w
 // placement pass; its length was set before the grid starts, so every loop
 // ends).  Each such wave's 64 spans (64 S bytes from the wave's first walk)
 // are split into shares of 64 S / kRewalkThreads bytes (rounded up to 16),
-// each walked with the m - 1 bytes after it twice from the start state: once
-// counting the matches that start in it, once writing them from its output
-// slot (the wave's slot plus a block scan of the counts).  The table is read
+// each walked with the m - 1 bytes after it from the start state, counting
+// the matches that start in it and keeping the first two; after a block scan
+// of the counts gives each share its output slot (after the wave's), a share
+// with at most two matches writes them from registers and one with more walks
+// again, writing as it goes (for m >= 12 a share rarely has more than one).
+// The table is read
 // through a pointer into dynamic LDS (the block scan's slots follow it
 // there).  256 groups (one per CU) cost less to launch than 1024 when the
 // list is short (a few microseconds per call) and measured the same on a
@@ -831,7 +834,8 @@ __device__ __forceinline__ void rewalk_fetch(const uint8_t *text, int64_t n, int
 
 template <bool WRITE>
 __device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n, const unsigned char *tab, uint32_t m,
-                                                 int64_t a, int64_t b, int64_t off, int64_t *positions, int64_t cap) {
+                                                 int64_t a, int64_t b, int64_t off, int64_t *positions, int64_t cap,
+                                                 int64_t &s0, int64_t &s1) {
     const int64_t lim = b + int64_t(m) - 1 < n ? b + int64_t(m) - 1 : n;
     uint32_t q = 0, c = 0;
     uint32_t cur[4], nxt[4];
@@ -842,7 +846,14 @@ __device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n,
         for (int k = 0; k < 16; ++k) {
             q = tab[q * uint32_t(kRow) + ((cur[k / 4] >> (8 * (k % 4))) & 0xffu)];
             if (q == m && j0 + k < lim) {
-                if (WRITE && off + c < cap) positions[off + c] = j0 + k - int64_t(m - 1);
+                const int64_t st = j0 + k - int64_t(m - 1);
+                if (WRITE) {
+                    if (off + c < cap) positions[off + c] = st;
+                } else if (c == 0) {
+                    s0 = st;
+                } else if (c == 1) {
+                    s1 = st;
+                }
                 ++c;
             }
         }
@@ -876,10 +887,16 @@ __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, 
         const int64_t end = start + kWave * S < n ? start + kWave * S : n;
         const int64_t a = start + t * share;
         const int64_t b = a + share < end ? a + share : end;
-        const uint32_t c = a < b ? rewalk_share<false>(text, n, smem, uint32_t(m), a, b, 0, nullptr, 0) : 0u;
+        int64_t s0 = 0, s1 = 0;  // the first two match starts, kept by the counting walk
+        const uint32_t c = a < b ? rewalk_share<false>(text, n, smem, uint32_t(m), a, b, 0, nullptr, 0, s0, s1) : 0u;
         unsigned long long total;
         const int64_t off = wave_off[gw] + int64_t(block_exclusive_scan(c, sh, &total));
-        if (c) rewalk_share<true>(text, n, smem, uint32_t(m), a, b, off, positions, cap);
+        if (c > 2) {
+            rewalk_share<true>(text, n, smem, uint32_t(m), a, b, off, positions, cap, s0, s1);
+        } else {
+            if (c > 0 && off < cap) positions[off] = s0;
+            if (c > 1 && off + 1 < cap) positions[off + 1] = s1;
+        }
     }
 }
 

@@ -155,6 +155,30 @@ def test_positions_truncated_to_cap_long_pattern():
         assert np.array_equal(pos.cpu().numpy(), np.arange(1234))
 
 
+def test_positions_truncated_to_cap_sparse_long_pattern():
+    """Per-wave plans with one or two matches per re-walked share (written from the counting
+    walk's registers) and with more (written by a second walk): the first `cap` positions
+    equal the oracle's, for caps that cut inside either kind of share."""
+    rng = np.random.default_rng(17)
+    n = 2_000_003
+    for m in (12, 16, 24, 40):
+        pat = synth.random_pattern(m, rng)
+        t = synth.genome_like(n, 30 + m, 0.0, 300)
+        for s0 in range(1000, n - 200, 45 + m):    # isolated matches, 45 + m bytes apart
+            t[s0:s0 + m] = np.frombuffer(pat, np.uint8)
+        if m <= 20:                                # and a burst of back-to-back repeats
+            burst = np.frombuffer(pat * (3000 // m), np.uint8)
+            t[500_000:500_000 + burst.size] = burst
+        want = oracle.occurrences(t, pat)
+        d = api.to_device(t)
+        tab, mm = api.device_table(pat)
+        for cap in (1, 2, 3, len(want) // 3, len(want) - 1):
+            say(f"sparse cap m={m} cap={cap} of {len(want)}")
+            c, pos = api.positions(d, tab, mm, cap=cap)
+            assert c == len(want)
+            assert np.array_equal(pos.cpu().numpy(), want[:cap])
+
+
 def test_repeatable_bit_equal():
     text = gc_text(5_000_000, 3)
     d = api.to_device(text)
