@@ -672,6 +672,7 @@ __global__ __launch_bounds__(kPartsThreads) void k_scan_parts(const unsigned lon
 constexpr int kPlaceThreads = 256;
 constexpr int kPlacePerThread = 8;
 constexpr int kPlaceWalks = kPlaceThreads * kPlacePerThread;
+constexpr int kPlaceUnroll = 4;  // buffered matches a thread places per iteration
 
 __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_count, const uint16_t *walk_buf,
                                                          const uint16_t *walk_buf1, const uint32_t *wg_waves,
@@ -747,21 +748,41 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
     }
     __syncthreads();
     if (t < per_block && wg0 + t < nb) wg_flag[wg0 + t] = over[t];
-    for (uint32_t k = t; k < nbuf; k += kPlaceThreads) {
-        // the walk holding buffered match k: the last w with first[w] <= k.
-        // Consecutive threads write consecutive positions (a thread writing a
-        // run of its own would scatter partial lines across the wave).
-        int lo = 0, hi = bw - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (first[mid] <= k) lo = mid; else hi = mid - 1;
+    // Buffered match k goes to the walk holding it: the last w with
+    // first[w] <= k (first[0] = 0 and first never decreases), found in a
+    // fixed number of halving steps.  Consecutive threads write consecutive
+    // positions (a thread writing a run of its own would scatter partial lines
+    // across the wave); each thread takes kPlaceUnroll matches per iteration,
+    // so that their searches interleave and their record loads are in flight
+    // together.
+    for (uint32_t k0 = t; k0 < nbuf; k0 += kPlaceUnroll * kPlaceThreads) {
+        int lo[kPlaceUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlaceUnroll; ++u) {
+            const uint32_t k = k0 + uint32_t(u * kPlaceThreads);
+            int l = 0;
+#pragma unroll
+            for (int step = kPlaceWalks / 2; step > 0; step >>= 1)
+                if (l + step < bw && first[l + step] <= k) l += step;
+            lo[u] = l;
         }
-        const uint32_t i = k - first[lo];
-        const int64_t dst = out[lo] + i;
-        const int64_t gw = g0 + lo;
-        if (dst < cap)
-            positions[dst] = gw * S + int64_t(i < uint32_t(kStaged) ? walk_buf[gw * kStaged + i]
-                                                                     : walk_buf1[gw * kStaged + i - kStaged]);
+        int64_t dst[kPlaceUnroll];
+        uint32_t rec[kPlaceUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlaceUnroll; ++u) {
+            const uint32_t k = k0 + uint32_t(u * kPlaceThreads);
+            const uint32_t i = k - first[lo[u]];
+            const int64_t gw = g0 + lo[u];
+            dst[u] = out[lo[u]] + i;
+            rec[u] = 0;
+            if (k < nbuf && dst[u] < cap)
+                rec[u] = i < uint32_t(kStaged) ? walk_buf[gw * kStaged + i] : walk_buf1[gw * kStaged + i - kStaged];
+        }
+#pragma unroll
+        for (int u = 0; u < kPlaceUnroll; ++u) {
+            const uint32_t k = k0 + uint32_t(u * kPlaceThreads);
+            if (k < nbuf && dst[u] < cap) positions[dst[u]] = (g0 + lo[u]) * S + int64_t(rec[u]);
+        }
     }
 }
 
