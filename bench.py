@@ -406,6 +406,7 @@ def bench_serving(torch, nq, warm=50, pool=64):
     cont = serve.summarize(res)
     fifo_res = srv.serve(timed, mode="fifo")
     fifo = serve.summarize(fifo_res)
+    srv.release_pinned()
     same = all(np.array_equal(x.counts, y.counts) for x, y in zip(res, fifo_res))
     total = sum(r.text.size for r in meas)
     return {"workload": f"{nq} queries after {warm} warm-up, text log-uniform [1e4, 5e8] B (2% N runs; "

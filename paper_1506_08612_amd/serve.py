@@ -143,7 +143,14 @@ class Server:
         self.tune = tune
         self.chunk_bytes = int(chunk_bytes)
         self.chunks_in_flight = int(chunks_in_flight)
+        # pinned host copies of the texts served so far, one per distinct array, kept so
+        # that a trace served again (or a text carried by many requests) is pinned once;
+        # release_pinned() gives the memory back
         self._pinned = {}
+
+    def release_pinned(self) -> None:
+        """Free the pinned host copies of every text served so far."""
+        self._pinned.clear()
 
     # -- helpers --------------------------------------------------------------------------
     def _pin(self, text: np.ndarray):

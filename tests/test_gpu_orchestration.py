@@ -92,6 +92,7 @@ def test_server_answers_match_oracle(mode):
     trace = _trace(24, rate=2000.0, seed=3)
     srv = serve.Server(arena_bytes=64 << 20)
     res = srv.serve(trace, mode=mode)
+    srv.release_pinned()
     for req, r in zip(trace, res):
         assert r.qid == req.qid
         assert np.array_equal(r.counts, _want(req)), req.qid
@@ -99,6 +100,10 @@ def test_server_answers_match_oracle(mode):
     s = serve.summarize(res)
     say(mode, s)
     assert s["queries"] == 24
+    # served again after the pinned copies were released: pinned anew, same answers
+    again = srv.serve([serve.Request(r.qid, r.text, r.patterns, 0.0) for r in trace[:3]], mode=mode)
+    for a, r in zip(again, res[:3]):
+        assert np.array_equal(a.counts, r.counts)
 
 
 def test_server_alone_equals_in_mix_with_admission_pressure():
