@@ -11,6 +11,7 @@ Cache location: $DFA_TUNE_CACHE, else ~/.cache/paper_1506_08612_amd/tune.json.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -75,10 +76,25 @@ def _store(d: dict) -> None:
         pass  # a read-only home only costs re-tuning
 
 
+_LIB_HASH = None
+
+
+def _lib_hash() -> str:
+    """Short hash of the built library: a rebuilt library (other kernels) tunes anew."""
+    global _LIB_HASH
+    if _LIB_HASH is None:
+        h = hashlib.sha256()
+        with open(api.LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _LIB_HASH = h.hexdigest()[:12]
+    return _LIB_HASH
+
+
 def device_key() -> str:
     import torch
     name = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
-    return f"{name}|{api.lib.dfa_version().decode()}"
+    return f"{name}|{api.lib.dfa_version().decode()}|{_lib_hash()}"
 
 
 def scan_class(n: int, m: int) -> str:

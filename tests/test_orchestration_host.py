@@ -66,3 +66,15 @@ def test_query_trace_shape():
     assert k.min() >= 1 and k.max() <= 64
     ms = np.concatenate([q.pattern_lens for q in tr])
     assert ms.min() >= 4 and ms.max() <= 64
+
+
+def test_tune_cache_key_names_the_built_library(tmp_path, monkeypatch):
+    from paper_1506_08612_amd import api, autotune
+    key = autotune.device_key()
+    assert key.endswith("|" + autotune._lib_hash()) and len(autotune._lib_hash()) == 12
+    # another library file (different kernels) gives another key
+    other = tmp_path / "libdfa.so"
+    other.write_bytes(open(api.LIB_PATH, "rb").read() + b"\0")
+    monkeypatch.setattr(api, "LIB_PATH", str(other))
+    monkeypatch.setattr(autotune, "_LIB_HASH", None)
+    assert autotune.device_key() != key
