@@ -128,9 +128,15 @@ struct Piece {
     uint32_t valid;      // bit j: byte j lies below the end of the unit
 };
 
-// The 16 bytes at p, all present (raw + p is 16-byte aligned).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The 16 bytes at p, all present (raw + p is 16-byte aligned).  NT: a
+// non-temporal load (the write pass, whose whole-line reads and 16-byte block
+// stores stream faster non-temporal; the summary pass measured no difference).
+template <bool NT>
 __device__ __forceinline__ Piece load_full(const uint8_t *raw, int64_t p) {
-    const uint4 v = *reinterpret_cast<const uint4 *>(raw + p);
+    const u32x4 v = NT ? __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(raw + p))
+                       : *reinterpret_cast<const u32x4 *>(raw + p);
     Piece x;
     x.w[0] = v.x;
     x.w[1] = v.y;
@@ -229,20 +235,20 @@ __device__ __forceinline__ int32_t last_start(const Lines &L, int32_t prel) {
 // its last whole piece again (a cache hit), so that the loads in flight are
 // the same on every path and each round waits for its own load only.  A last,
 // partial round (the end of the text) comes after them.
-template <class Step>
+template <bool NT, class Step>
 __device__ __forceinline__ void unit_rounds(const uint8_t *raw, int64_t u0, int64_t u1, Step &&step) {
     const int full = int((u1 - u0) / kRound);
     const int64_t lp = int64_t(__lane_id()) * kPer;
     if (full > 0) {
         const auto at = [&](int r) { return u0 + int64_t(r < full ? r : full - 1) * kRound + lp; };
-        Piece a = load_full(raw, at(0)), b = load_full(raw, at(1)), c = load_full(raw, at(2));
+        Piece a = load_full<NT>(raw, at(0)), b = load_full<NT>(raw, at(1)), c = load_full<NT>(raw, at(2));
         for (int r = 0; r < full; r += 3) {
             step(a, r);
-            a = load_full(raw, at(r + 3));
+            a = load_full<NT>(raw, at(r + 3));
             if (r + 1 < full) step(b, r + 1);
-            b = load_full(raw, at(r + 4));
+            b = load_full<NT>(raw, at(r + 4));
             if (r + 2 < full) step(c, r + 2);
-            c = load_full(raw, at(r + 5));
+            c = load_full<NT>(raw, at(r + 5));
         }
     }
     if (u0 + int64_t(full) * kRound < u1) step(load_tail(raw, u1, u0 + int64_t(full) * kRound + lp), full);
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
     int32_t carry_nl = u0 == 0 ? 1 : int32_t(raw[u0 - 1] == kNl);
     int32_t carry = kNone;
     uint32_t pre = 0, kept = 0, hdr = 0;
-    unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
+    unit_rounds<false>(raw, u0, u1, [&](const Piece &x, int r) {
         const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
         const Lines L = analyse(x, nl, prev);
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
     const int64_t head_end = o_start + ((16u - ((abase + uint32_t(o_start)) & 15u)) & 15u);
     int64_t f = o_start;  // output below f is stored
     bool head_done = head_end == o_start;
-    unit_rounds(raw, u0, u1, [&](const Piece &x, int r) {
+    unit_rounds<true>(raw, u0, u1, [&](const Piece &x, int r) {
         const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
         const Lines L = analyse(x, nl, prev);
@@ -471,8 +477,8 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
             const int64_t end = o - int64_t((abase + uint32_t(o)) & 15u);
             for (int64_t k = lane; f + 16 * k < end; k += kWaveSize) {
                 const int64_t q = f + 16 * k;
-                const uint4 v = *reinterpret_cast<const uint4 *>(ring + ((abase + uint32_t(q)) & kMask));
-                if (q >= 0 && q + 16 <= n) *reinterpret_cast<uint4 *>(out + q) = v;
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(ring + ((abase + uint32_t(q)) & kMask));
+                if (q >= 0 && q + 16 <= n) __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(out + q));
             }
             f = std::max(f, end);
         }
