@@ -30,7 +30,8 @@
 // each other.  C stages a round's kept bytes in a per-wave LDS ring indexed
 // by output address and stores whole aligned 16-byte blocks; the partial
 // blocks at a unit's two ends, shared with the neighbouring units, are
-// stored byte by byte.
+// stored byte by byte.  C's text loads and block stores are non-temporal:
+// each byte is read or written once.
 
 #include <hip/hip_runtime.h>
 
