@@ -513,7 +513,8 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
                     const uint32_t hi = *reinterpret_cast<const lds_u16w *>(uintptr_t(a + 2u * kWave));
                     r[k] = lo | (hi << 16);
                 }
-                *reinterpret_cast<uint4 *>(p.walk_buf + lane * kStaged) = make_uint4(r[0], r[1], r[2], r[3]);
+                const v4u rec = {r[0], r[1], r[2], r[3]};
+                __builtin_nontemporal_store(rec, reinterpret_cast<v4u *>(p.walk_buf + lane * kStaged));
             }
         }
         // the wave's matches, summed over its lanes
@@ -781,7 +782,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint32_t *walk_co
 #pragma unroll
         for (int u = 0; u < kPlaceUnroll; ++u) {
             const uint32_t k = k0 + uint32_t(u * kPlaceThreads);
-            if (k < nbuf && dst[u] < cap) positions[dst[u]] = (g0 + lo[u]) * S + int64_t(rec[u]);
+            if (k < nbuf && dst[u] < cap)
+                __builtin_nontemporal_store((g0 + lo[u]) * S + int64_t(rec[u]), positions + dst[u]);
         }
     }
 }
