@@ -306,7 +306,8 @@ int64_t dfa_fasta_workspace_bytes(int64_t n);
  * plain sequence: a line whose first byte is '>' is a header (it starts a
  * record; none of its bytes are kept); every other byte is kept except '\n'
  * and '\r', with 'a'..'z' made upper case (soft-masking dropped).
- *   out        device, room for n bytes: the kept bytes, in order
+ *   out        device, room for n bytes, any alignment: the kept bytes, in
+ *              order (no byte of out past them is written)
  *   rec_start  device int64, room for rec_cap entries: where each record's
  *              sequence starts in `out` (the first rec_cap records)
  *   totals     device int64[2]: {kept bytes, records} (exact even past rec_cap)
