@@ -234,9 +234,10 @@ def count_async(text, table, m: int, count_out, positions_out=None, cap: int = 0
 def count(text, table, m: int, t: Optional[Tune] = None, stream=None) -> int:
     """Exact overlapping match count (synchronises the stream)."""
     torch = _torch()
-    out = torch.empty(1, dtype=torch.int64, device=text.device)
-    count_async(text, table, m, out, t=t, stream=stream)
-    return int(out.item())
+    with torch.cuda.stream(stream):
+        out = torch.empty(1, dtype=torch.int64, device=text.device)
+        count_async(text, table, m, out, t=t, stream=stream)
+        return int(out.item())
 
 
 def positions(text, table, m: int, cap: Optional[int] = None, t: Optional[Tune] = None,
@@ -246,29 +247,31 @@ def positions(text, table, m: int, cap: Optional[int] = None, t: Optional[Tune] 
     torch = _torch()
     n = text.numel()
     dev = text.device
-    out = torch.empty(1, dtype=torch.int64, device=dev)
-    if cap is None:
-        count_async(text, table, m, out, t=t, stream=stream)
-        cap = int(out.item())
-    pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=dev)
-    wsb = count_workspace_bytes(n, m, True, t)
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
-    count_async(text, table, m, out, pos, cap, ws, t=t, stream=stream)
-    c = int(out.item())
-    return c, pos[:min(c, int(cap))]
+    with torch.cuda.stream(stream):
+        out = torch.empty(1, dtype=torch.int64, device=dev)
+        if cap is None:
+            count_async(text, table, m, out, t=t, stream=stream)
+            cap = int(out.item())
+        pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=dev)
+        wsb = count_workspace_bytes(n, m, True, t)
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        count_async(text, table, m, out, pos, cap, ws, t=t, stream=stream)
+        c = int(out.item())
+        return c, pos[:min(c, int(cap))]
 
 
 def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_cap: int = 1 << 22):
     """Count-only scan that also records every workgroup's start/end (wall clock) and
     cycles: returns (count, int64 array of shape (workgroups, 3)) (synchronises)."""
     torch = _torch()
-    out = torch.empty(1, dtype=torch.int64, device=text.device)
-    times = torch.zeros(3 * wg_cap, dtype=torch.int64, device=text.device)
-    tab = _ptr(table, "uint8", "table", (int(m) + 1) * ALPHABET if 1 <= m <= MAX_M else 0)
-    nb = _check(lib.dfa_count_timed(_ptr(text, "uint8", "text"), text.numel(), tab, m, out.data_ptr(),
-                                    times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
-    k = min(nb, wg_cap)
-    return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
+    with torch.cuda.stream(stream):
+        out = torch.empty(1, dtype=torch.int64, device=text.device)
+        times = torch.zeros(3 * wg_cap, dtype=torch.int64, device=text.device)
+        tab = _ptr(table, "uint8", "table", (int(m) + 1) * ALPHABET if 1 <= m <= MAX_M else 0)
+        nb = _check(lib.dfa_count_timed(_ptr(text, "uint8", "text"), text.numel(), tab, m, out.data_ptr(),
+                                        times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
+        k = min(nb, wg_cap)
+        return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
 
 
 class ScanEvents:
@@ -357,8 +360,9 @@ class Batch:
 def count_batch(text, seg_off, pset: PatternSet, pair_seg, pair_pat, t: Optional[Tune] = None,
                 stream=None) -> np.ndarray:
     """Per-pair occurrence counts (synchronises)."""
-    b = Batch(seg_off, pset, pair_seg, pair_pat, t, stream)
-    return b.run(text, stream).cpu().numpy()
+    with _torch().cuda.stream(stream):
+        b = Batch(seg_off, pset, pair_seg, pair_pat, t, stream)
+        return b.run(text, stream).cpu().numpy()
 
 
 # ---------------------------------------------------------------------------
@@ -452,8 +456,9 @@ class MergedBatch:
 def count_merged(text, seg_off, patterns, pair_seg, pair_pat, t: Optional[Tune] = None,
                  stream=None) -> np.ndarray:
     """Per-pair occurrence counts with merged automata (synchronises)."""
-    b = MergedBatch(seg_off, patterns, pair_seg, pair_pat, t, device=text.device, stream=stream)
-    return b.run(text, stream).cpu().numpy()
+    with _torch().cuda.stream(stream):
+        b = MergedBatch(seg_off, patterns, pair_seg, pair_pat, t, device=text.device, stream=stream)
+        return b.run(text, stream).cpu().numpy()
 
 
 # ---------------------------------------------------------------------------
@@ -499,8 +504,9 @@ class DegenerateBatch:
 
 def count_degenerate(text, seg_off, queries, t: Optional[Tune] = None, stream=None) -> np.ndarray:
     """Per-query counts of degenerate patterns (synchronises)."""
-    b = DegenerateBatch(seg_off, queries, t, device=text.device, stream=stream)
-    return b.run(text, stream).cpu().numpy()
+    with _torch().cuda.stream(stream):
+        b = DegenerateBatch(seg_off, queries, t, device=text.device, stream=stream)
+        return b.run(text, stream).cpu().numpy()
 
 
 # ---------------------------------------------------------------------------
@@ -515,15 +521,16 @@ def fasta_normalize(raw, rec_cap: int = 1 << 16, stream=None):
     src = _ptr(raw, "uint8", "raw")
     n = raw.numel()
     dev = raw.device
-    out = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
-    rec = torch.empty(max(1, rec_cap), dtype=torch.int64, device=dev)
-    tot = torch.zeros(2, dtype=torch.int64, device=dev)
-    wsb = _check(lib.dfa_fasta_workspace_bytes(n))
-    ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=dev)
-    _check(lib.dfa_fasta_normalize(src, n, out.data_ptr(), rec.data_ptr(), rec_cap,
-                                   tot.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
-    kept, nrec = (int(x) for x in tot.cpu().tolist())
-    return out[:kept], rec[:min(nrec, rec_cap)], kept, nrec
+    with torch.cuda.stream(stream):
+        out = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+        rec = torch.empty(max(1, rec_cap), dtype=torch.int64, device=dev)
+        tot = torch.zeros(2, dtype=torch.int64, device=dev)
+        wsb = _check(lib.dfa_fasta_workspace_bytes(n))
+        ws = torch.empty(max(256, wsb), dtype=torch.uint8, device=dev)
+        _check(lib.dfa_fasta_normalize(src, n, out.data_ptr(), rec.data_ptr(), rec_cap,
+                                       tot.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+        kept, nrec = (int(x) for x in tot.cpu().tolist())
+        return out[:kept], rec[:min(nrec, rec_cap)], kept, nrec
 
 
 def exported_symbols() -> Sequence[str]:

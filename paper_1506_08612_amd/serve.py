@@ -80,8 +80,12 @@ class Arena:
 def segments_for(placed, arena_size: int):
     """Segment boundaries covering [0, end of the last text) for texts placed at
     (offset, length): every text is a segment; the gaps between texts are segments
-    too (no pair refers to them).  Returns (seg_off, seg_of_text)."""
-    order = sorted(range(len(placed)), key=lambda i: placed[i][0])
+    too (no pair refers to them).  Returns (seg_off, seg_of_text).
+
+    An empty text is placed at offset 0 without taking arena space, so it may share
+    its offset with a text that starts there; ordering by (offset, length) puts the
+    empty one first and keeps the offsets non-decreasing."""
+    order = sorted(range(len(placed)), key=lambda i: (placed[i][0], placed[i][1]))
     seg_off = [0]
     seg_of = [0] * len(placed)
     for i in order:

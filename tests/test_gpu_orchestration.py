@@ -132,3 +132,25 @@ def test_server_edge_requests():
     for req, r in zip(reqs, res):
         assert np.array_equal(r.counts, _want(req)), req.qid
     del rng
+
+
+def test_server_fuses_empty_request_after_text_at_offset_zero():
+    """An empty request shares offset 0 with the text placed there; fused into one launch
+    after it, both answers must be exact."""
+    text = synth.iid_gc41(50_000, 11)
+    reqs = [serve.Request(0, text, [b"ACGT", b"GATTACA", bytes(text[100:112])], 0.0),
+            serve.Request(1, np.zeros(0, np.uint8), [b"ACGT", b"A"], 0.0)]
+    srv = serve.Server(arena_bytes=1 << 20)
+    srv.arena_buf[:text.size].copy_(torch.from_numpy(text))
+    jobs = []
+    for r in reqs:
+        j = serve._Job()
+        j.req, j.pinned, j.offset = r, None, 0
+        j.admitted = j.launched = 0.0
+        j.next_byte, j.pending_events = r.text.size, 0
+        jobs.append(j)
+    ev, counts, spans, keep = srv._launch(jobs)
+    ev.synchronize()
+    c = counts.cpu().numpy()
+    for (a, b), r in zip(spans, reqs):
+        assert np.array_equal(c[a:b], _want(r)), r.qid

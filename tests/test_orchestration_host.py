@@ -55,6 +55,16 @@ def test_segments_cover_texts_and_gaps():
         assert seg_off[s] == off and seg_off[s + 1] == off + ln
 
 
+def test_segments_empty_text_sharing_offset_zero():
+    # an empty text is placed at offset 0 without arena space; fused after a text that
+    # starts at 0, the offsets must still be non-decreasing and both segments exact
+    for placed in ([(0, 1000), (0, 0)], [(0, 0), (0, 1000)], [(0, 1000), (0, 0), (0, 0), (1024, 5)]):
+        seg_off, seg_of = segments_for(placed, 1 << 20)
+        assert (np.diff(seg_off) >= 0).all() and seg_off[0] == 0, placed
+        for (off, ln), s in zip(placed, seg_of):
+            assert seg_off[s] == off and seg_off[s + 1] == off + ln, placed
+
+
 def test_query_trace_shape():
     tr = synth.query_trace(200, 50.0, seed=1, len_lo=1e4, len_hi=5e8)
     t = np.array([q.arrival_s for q in tr])
