@@ -226,3 +226,26 @@ def test_binding_rejects_bad_tensors():
     with pytest.raises(ValueError, match="contiguous"):
         api.fasta_normalize(d[::2])
     assert api.count(d, tab, m) == 64  # the same tensors, well formed
+
+
+@pytest.mark.parametrize("n,m,chain", [(1, 1, 0), (1000, 4, 0), ((1 << 20) + 13, 8, 0), ((1 << 20) + 13, 8, 4096),
+                                        (50_000_017, 4, 0), (50_000_017, 32, 0), (3_000_001, 200, 512)])
+def test_count_timed_matches_oracle(n, m, chain):
+    """The load-balance study's entry point: its count equals the oracle's, every launched
+    workgroup leaves an ordered, non-zero record, and a short record buffer is respected."""
+    text = gc_text(n, 31 + n % 7, plant=None)
+    pat = synth.drawn_pattern(text, m, np.random.default_rng(n + m))[0] or b"A" * m
+    d = api.to_device(text)
+    tab, mm = api.device_table(pat)
+    t = api.tune(chain_bytes=chain) if chain else None
+    c, rows = api.count_timed(d, tab, mm, t=t)
+    assert c == oracle.count(text, pat), (n, m)
+    assert c == api.count(d, tab, mm, t=t)
+    nb = rows.shape[0]
+    assert nb >= 1
+    start, end, cyc = rows[:, 0], rows[:, 1], rows[:, 2]
+    assert (start > 0).all() and (end >= start).all() and (cyc > 0).all(), (n, m)
+    assert end.max() - start.min() < 10 * 100_000_000  # the launch spans under 10 s of the 100 MHz clock
+    # room for only three workgroups: the count is unchanged and only those rows are written
+    c3, rows3 = api.count_timed(d, tab, mm, t=t, wg_cap=3)
+    assert c3 == c and rows3.shape[0] == min(3, nb) and (rows3[:, 2] > 0).all()
