@@ -132,6 +132,22 @@ int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, in
                         int64_t *count, unsigned long long *wg_times, int64_t wg_cap,
                         const dfa_tune *tune, void *stream);
 
+/* Measurement only: the LDS gather rate of the current GPU, the ceiling of
+ * the table reads every automaton step makes (Alg. 1; the sparse transition
+ * table of Sec. III.B, held in LDS here).  Launches `blocks` workgroups of 512
+ * threads; each thread makes iters x 8 reads of `width` bytes (1 or 2) from a
+ * 16 KiB LDS table, at addresses independent of the values read
+ * (dependent = 0: the gather throughput) or, in 8 chains per thread, computed
+ * from the chain's previous value as value x row + column (dependent = 1: an
+ * automaton step's dependent read).  `sink` (device, 8 bytes, 8-byte aligned)
+ * is written only in a case that does not occur; it keeps the reads.
+ * Returns the number of reads launched (time the launch on `stream` to get
+ * the rate), or DFA_EINVAL (width, dependent, blocks in [1, 2^20] or iters in
+ * [1, 2^24] out of range, null or misaligned sink) / DFA_EHIP. */
+int64_t dfa_lds_probe(int32_t width, int32_t dependent, int32_t blocks, int64_t iters,
+                      unsigned long long *sink, void *stream);
+
+
 /* ------------------------------------------------------------------------ */
 /* Batched: many patterns over many texts in one launch.                    */
 /* ------------------------------------------------------------------------ */

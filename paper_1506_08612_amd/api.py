@@ -100,6 +100,7 @@ SIGNATURES = {
     "dfa_count_workspace_bytes": (_i64, [_i64, _i32, _i32, _TuneP]),
     "dfa_count": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP, _vp]),
     "dfa_count_timed": (_i64, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _TuneP, _vp]),
+    "dfa_lds_probe": (_i64, [_i32, _i32, _i32, _i64, _vp, _vp]),
     "dfa_set_scan_events": (ctypes.c_int, [_vp, _vp]),
     "dfa_batch_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
                                          _PlanP, _vp]),
@@ -272,6 +273,12 @@ def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_c
                                         times.data_ptr(), wg_cap, _tune_ptr(t), _stream_handle(stream)))
         k = min(nb, wg_cap)
         return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
+
+
+def lds_probe(width: int, dependent: bool, blocks: int, iters: int, sink, stream=None) -> int:
+    """Enqueue the LDS gather probe; returns the number of reads it makes."""
+    return _check(lib.dfa_lds_probe(int(width), int(bool(dependent)), int(blocks), int(iters),
+                                    _ptr(sink, "int64", "sink", 1), _stream_handle(stream)))
 
 
 class ScanEvents:

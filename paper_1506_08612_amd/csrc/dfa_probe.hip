@@ -1,0 +1,121 @@
+// LDS gather rate of the device (measurement only).
+//
+// Every automaton step of the paper's scan is one table read at an address
+// that depends on the state and the text byte (Alg. 1; the sparse transition
+// table of Sec. III.B).  On gfx950 the tables live in LDS, so the rate at
+// which LDS serves single-byte and two-byte reads at scattered addresses is
+// the ceiling of every table-bound scan here (the merged multi-pattern scan
+// above all).  This kernel measures that rate two ways:
+//
+//   independent  eight reads per lane and iteration at addresses that do not
+//                depend on the values read (a lane's base plus fixed
+//                offsets): the gather throughput;
+//   dependent    eight chains per lane, each read's address computed from the
+//                previous value of its chain as an automaton step computes
+//                the next row from the state (value x row + column): the
+//                rate a walk reaches when every lane has eight walks in
+//                flight.
+//
+// The table is 16 KiB of values below 128 (a row number), every address is
+// inside it by construction, and the loaded values are kept alive by a store
+// that only an impossible checksum would make.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dfa.h"
+#include "dfa_internal.h"
+#include "launch_util.h"
+
+namespace {
+
+constexpr int kProbeBytes = 16 * 1024;
+constexpr int kProbeThreads = 512;
+constexpr int kReadsPerIter = 8;
+constexpr uint32_t kStride = 1022;   // bytes between a lane's independent reads (even)
+constexpr uint32_t kAdvance = 2474;  // bytes a lane's base moves per iteration (even)
+
+typedef __attribute__((address_space(3))) const uint8_t lds8;
+typedef __attribute__((address_space(3))) const uint16_t lds16;
+
+__device__ __forceinline__ uint32_t mix(uint32_t x) {  // a 32-bit integer hash (xorshift-multiply)
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int WIDTH>
+__device__ __forceinline__ uint32_t lds_read(uint32_t addr) {
+    if (WIDTH == 1) return *reinterpret_cast<lds8 *>(uintptr_t(addr));
+    return *reinterpret_cast<lds16 *>(uintptr_t(addr));
+}
+
+template <int WIDTH, bool DEP>
+__global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsigned long long *sink) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // values below 128: one byte each, or the low byte of each 16-bit entry
+    const uint32_t keep = WIDTH == 1 ? 0x7f7f7f7fu : 0x007f007fu;
+    for (int i = threadIdx.x; i < kProbeBytes / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(smem)[i] = mix(uint32_t(i) * 2654435761u + 12345u) & keep;
+    __syncthreads();
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    if (!DEP) {
+        // base < 8 KiB, offsets <= 7 x 1022: every address < 16 KiB; even for 2-byte reads
+        uint32_t base = mix(tid) & uint32_t(kProbeBytes / 2 - WIDTH);
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int c = 0; c < kReadsPerIter; ++c) acc += lds_read<WIDTH>(base + uint32_t(c) * kStride);
+            base = (base + kAdvance) & uint32_t(kProbeBytes / 2 - WIDTH);
+        }
+    } else {
+        // row = value (< 128) x 128 bytes (1-byte entries) or x 64 entries (2-byte), column < 128 / 64
+        uint32_t v[kReadsPerIter];
+#pragma unroll
+        for (int c = 0; c < kReadsPerIter; ++c) v[c] = mix(tid * kReadsPerIter + c) & 127u;
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int c = 0; c < kReadsPerIter; ++c) {
+                if (WIDTH == 1)
+                    v[c] = lds_read<1>(__umul24(v[c], 128u) + uint32_t(13 * c));
+                else
+                    v[c] = lds_read<2>(2u * (__umul24(v[c], 64u) + uint32_t(7 * c)));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kReadsPerIter; ++c) acc += v[c];
+    }
+    if (acc == 0xffffffffu) sink[0] = acc;  // never true (values < 128): keeps the reads
+}
+
+const void *probe_fn(int width, int dep) {
+    if (width == 1) return dep ? reinterpret_cast<const void *>(&k_lds_probe<1, true>)
+                               : reinterpret_cast<const void *>(&k_lds_probe<1, false>);
+    return dep ? reinterpret_cast<const void *>(&k_lds_probe<2, true>)
+               : reinterpret_cast<const void *>(&k_lds_probe<2, false>);
+}
+
+}  // namespace
+
+extern "C" int64_t dfa_lds_probe(int32_t width, int32_t dependent, int32_t blocks, int64_t iters,
+                                 unsigned long long *sink, void *stream) {
+    if ((width != 1 && width != 2) || (dependent != 0 && dependent != 1) || blocks < 1 || blocks > (1 << 20) ||
+        iters < 1 || iters > (int64_t(1) << 24) || !sink || (reinterpret_cast<uintptr_t>(sink) & 7)) {
+        dfa::set_error("dfa_lds_probe: bad arguments");
+        return DFA_EINVAL;
+    }
+    const void *fn = probe_fn(width, dependent);
+    if (!dfa::allow_lds(fn, kProbeBytes)) return DFA_EHIP;
+    int64_t it = iters;
+    void *args[] = {&it, &sink};
+    if (!dfa::hip_ok(hipLaunchKernel(fn, dim3(unsigned(blocks)), dim3(kProbeThreads), args, kProbeBytes,
+                                     reinterpret_cast<hipStream_t>(stream)),
+                     "k_lds_probe launch"))
+        return DFA_EHIP;
+    dfa::clear_error();
+    return int64_t(blocks) * kProbeThreads * iters * kReadsPerIter;
+}
