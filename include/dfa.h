@@ -147,6 +147,24 @@ int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, in
 int64_t dfa_lds_probe(int32_t width, int32_t dependent, int32_t blocks, int64_t iters,
                       unsigned long long *sink, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dfa_count
+ * with the positions workspace taken from a buffer the library itself holds
+ * in device memory, DFA_NOALLOC_SCRATCH_BYTES per GPU, kept from the first
+ * call on that GPU until the process ends.  The call allocates nothing.
+ * Arguments, results and errors are dfa_count's (same kernels, same output),
+ * without workspace / workspace_bytes; the scratch belongs to the device
+ * current on the calling thread.  When positions are asked for and
+ * dfa_count_workspace_bytes(n, m, 1, tune) exceeds DFA_NOALLOC_SCRATCH_BYTES
+ * (with the default tune: n above about 770 MB), it returns DFA_ENOSPACE and
+ * launches nothing.  Every call on one GPU uses the same scratch: calls that
+ * overlap on a GPU (on different streams, or from different threads without
+ * ordering) race and give undefined results; calls ordered on one stream are
+ * safe, each one initialises what it reads. */
+#define DFA_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int dfa_count_noalloc(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
+                      int64_t *count, int64_t *positions, int64_t cap,
+                      const dfa_tune *tune, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched: many patterns over many texts in one launch.                    */

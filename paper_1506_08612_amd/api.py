@@ -25,6 +25,7 @@ DFA_EINVAL = -1
 DFA_EHIP = -2
 DFA_ENOSPACE = -3
 MAX_M = 255
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DFA_NOALLOC_SCRATCH_BYTES
 ALPHABET = 256
 
 
@@ -100,6 +101,7 @@ SIGNATURES = {
     "dfa_count_workspace_bytes": (_i64, [_i64, _i32, _i32, _TuneP]),
     "dfa_count": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP, _vp]),
     "dfa_count_timed": (_i64, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _TuneP, _vp]),
+    "dfa_count_noalloc": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _TuneP, _vp]),
     "dfa_lds_probe": (_i64, [_i32, _i32, _i32, _i64, _vp, _vp]),
     "dfa_set_scan_events": (ctypes.c_int, [_vp, _vp]),
     "dfa_batch_prepare": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i64, _vp, _i64, _TuneP,
@@ -230,6 +232,19 @@ def count_async(text, table, m: int, count_out, positions_out=None, cap: int = 0
     wsp = _ptr(workspace, "uint8", "workspace") if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
     _check(lib.dfa_count(txt, n, tab, m, cnt, pos, int(cap), wsp, wsb, _tune_ptr(t), _stream_handle(stream)))
+
+
+def count_noalloc_async(text, table, m: int, count_out, positions_out=None, cap: int = 0,
+                        t: Optional[Tune] = None, stream=None) -> None:
+    """Enqueue dfa_count_noalloc: dfa_count with the positions workspace taken from the
+    library's own device scratch (no allocation by the library; calls that overlap on one
+    GPU race)."""
+    txt = _ptr(text, "uint8", "text")
+    tab = _ptr(table, "uint8", "table", (int(m) + 1) * ALPHABET if 1 <= m <= MAX_M else 0)
+    cnt = _ptr(count_out, "int64", "count_out", 1)
+    pos = _ptr(positions_out, "int64", "positions_out", int(cap)) if positions_out is not None else None
+    _check(lib.dfa_count_noalloc(txt, text.numel(), tab, m, cnt, pos, int(cap), _tune_ptr(t),
+                                 _stream_handle(stream)))
 
 
 def count(text, table, m: int, t: Optional[Tune] = None, stream=None) -> int:

@@ -1326,6 +1326,65 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// dfa_count without a caller workspace: the positions workspace lives in a
+// device array of the library, one copy per GPU.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// the device address of the current GPU's copy is looked up once per device
+// and used everywhere instead.  The positions path initialises every part of
+// its workspace it reads (workgroup totals, wave masks, prefixes, the list
+// length and the flags are written by the kernels of each call before they
+// are read), so the contents a previous call left behind do not matter.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[DFA_NOALLOC_SCRATCH_BYTES];
+
+// Device address of the current GPU's scratch, or nullptr (error set).
+void *scratch_on_current_device() {
+    static std::mutex mu;
+    static std::map<int, void *> addr;  // device ordinal -> address of its copy
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void *ptr = nullptr;
+    if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return nullptr;
+    if (!ptr) {
+        dfa::set_error("hipGetSymbolAddress(scratch) returned a null address");
+        return nullptr;
+    }
+    addr[dev] = ptr;
+    return ptr;
+}
+
+}  // namespace
+
+extern "C" int dfa_count_noalloc(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m,
+                                 int64_t *count, int64_t *positions, int64_t cap, const dfa_tune *tune,
+                                 void *stream) {
+    const bool want_pos = positions != nullptr && cap > 0;
+    int64_t need = 0;
+    if (want_pos) {
+        need = dfa_count_workspace_bytes(n, m, 1, tune);
+        if (need < 0) return int(need);  // bad n, m or tune: message set
+        if (need > DFA_NOALLOC_SCRATCH_BYTES) {
+            dfa::set_error("dfa_count_noalloc: positions of n=%lld need %lld bytes of workspace, above the "
+                           "library's %lld-byte scratch (use dfa_count with a caller workspace)",
+                           (long long)n, (long long)need, (long long)DFA_NOALLOC_SCRATCH_BYTES);
+            return DFA_ENOSPACE;
+        }
+    }
+    void *ws = nullptr;
+    if (need > 0) {
+        ws = scratch_on_current_device();
+        if (!ws) return DFA_EHIP;
+    }
+    return dfa_count(text, n, table, m, count, positions, cap, ws, need, tune, stream);
+}
+
 extern "C" int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, int32_t m, int64_t *count,
                                    unsigned long long *wg_times, int64_t wg_cap, const dfa_tune *tune, void *stream) {
     if (n <= 0 || m < 1 || m > DFA_MAX_M || !text || !table || !count || wg_cap < 0 || (wg_cap > 0 && !wg_times)) {

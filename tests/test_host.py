@@ -257,3 +257,19 @@ def test_scan_events_hook_arguments():
     assert "both events" in api.last_error()
     assert api.lib.dfa_set_scan_events(None, ctypes.c_void_p(16)) == api.DFA_EINVAL
     assert api.lib.dfa_set_scan_events(None, None) == api.DFA_OK
+
+
+def test_noalloc_scratch_limit_checked_on_the_host():
+    """dfa_count_noalloc refuses, before touching any device, positions whose workspace
+    would not fit the library's scratch; the binding's constant is the header's."""
+    src = open(os.path.join(ROOT, "include", "dfa.h")).read()
+    m = re.search(r"#define DFA_NOALLOC_SCRATCH_BYTES \((\d+)LL << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == api.NOALLOC_SCRATCH_BYTES
+    n = 1_000_000_000
+    assert api.count_workspace_bytes(n, 8, True) > api.NOALLOC_SCRATCH_BYTES
+    fake = 1 << 20  # never dereferenced: the size check comes first
+    rc = api.lib.dfa_count_noalloc(fake, n, fake, 8, fake, fake, 1, None, None)
+    assert rc == api.DFA_ENOSPACE and "scratch" in api.last_error()
+    # bad arguments are still EINVAL
+    assert api.lib.dfa_count_noalloc(fake, -1, fake, 8, fake, fake, 1, None, None) == api.DFA_EINVAL
+    assert api.lib.dfa_count_noalloc(fake, 100, fake, 0, fake, fake, 1, None, None) == api.DFA_EINVAL
