@@ -18,9 +18,14 @@ Also reported:
 * read_reduce_GBps -- a trivial read-reduce over the same device buffer (torch's
   sum of its 8-byte words), the streaming-read rate reached in the same run, and
   both scans' fractions of it;
-* cpu_baseline -- the CPU oracle (plain C, one thread) timed on a bounded
-  prefix of the same text for the same five patterns; the batched and
-  segmented legs carry their own, job-parallel over the host's cores;
+* cpu_baseline -- the CPU oracle's plain automaton scan (C, one thread) over the
+  whole text for the same five patterns, count + positions, every output checked
+  against the GPU's; beside it the definition (window compare) on a prefix; the
+  batched and segmented legs carry their own, job-parallel over the host's cores;
+* lds -- the LDS read rate of this GPU (dfa_lds_probe), the measured ceiling the
+  batched leg's LDS bound is taken against;
+* study -- the count-only scan over genome sizes 0.2..3.2 GB and the spread of
+  its workgroup durations (dfa_count_timed);
 * per-pattern latency p50/p99 of the full call (events around each call, in the
   second run of the steps);
 * batched -- 1 GB GC-41% text x 1024 patterns (lengths 4..64, half drawn from
@@ -59,8 +64,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "text GB/s (and % of HBM peak) single-pattern; pattern-bytes/s batched; p50/p99"
-# LDS reads of 2 bytes the device can serve per second: 256 CUs x 2.4 GHz x 64 lanes
-LDS_PEAK_LOOKUPS = 256 * 2.4e9 * 64
+# compute-unit clocks per second: 256 CUs at 2.4 GHz
+CU_CLOCKS_PER_S = 256 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 PATTERN_LENGTHS = (4, 8, 16, 32, 64)
 SCAN_SOURCES = [os.path.join(ROOT, "paper_1506_08612_amd", "csrc", f) for f in ("dfa_scan.hip", "walk_common.h")]
@@ -142,6 +147,37 @@ def _events_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def cpu_automaton_baseline(text, pats, counts, pos_bufs):
+    """The oracle's plain automaton scan (its C function, one thread) over the whole text for
+    every pattern: count and positions in one pass into a buffer sized from the GPU's count;
+    returns the baseline and whether every count and position equals the GPU's."""
+    import ctypes
+    o = oracle_mod()
+    lib = o._load().lib
+    u8p, i64p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int64)
+    n = text.size
+    secs, ok = 0.0, True
+    for i, p in enumerate(pats):
+        tab = np.ascontiguousarray(o.transition_table(p))
+        out = np.empty(max(1, counts[i]), np.int64)
+        t0 = time.perf_counter()
+        c = lib.oracle_automaton_scan(tab.ctypes.data_as(u8p), len(p), text.ctypes.data_as(u8p), n,
+                                      out.ctypes.data_as(i64p), out.size)
+        secs += time.perf_counter() - t0
+        g = pos_bufs[i][:counts[i]].cpu().numpy()
+        ok &= bool(c == counts[i] and np.array_equal(out[:c], g))
+        log(f"  cpu automaton scan m={len(p)}: {c} matches")
+    return ({"value": round(n * len(pats) / secs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+             "sample": f"the whole {n}-byte text, the same {len(pats)} patterns one after another: "
+                       f"the oracle's automaton scan (build of the table excluded), count + positions "
+                       f"in one pass, {secs:.1f} s on {cpu_model()}"}, ok)
+
+
 def cpu_pairs_baseline(text, seg_off, patterns, pair_seg, pair_pat, budget):
     """The oracle's per-(segment, pattern) count, job-parallel over the host's cores (one
     single-thread scan per job, on threads: the C call releases the interpreter lock), on the
@@ -171,9 +207,11 @@ def cpu_pairs_baseline(text, seg_off, patterns, pair_seg, pair_pat, budget):
                       f"job-parallel over {cores} threads, {wall:.1f} s on {cpu_model()}"}
 
 
-def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
+def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024, lds_peak=None):
     from paper_1506_08612_amd import autotune, graph
     log(f"batched: {n} bytes x {npat} patterns")
+    if lds_peak is None:
+        lds_peak = bench_lds(torch, api)["u16_conflict_free"]["reads_per_s"]
     w = synth.many_patterns(n=n, npat=npat)
     d = api.to_device(w.text)
     ps = api.PatternSet(w.patterns)
@@ -207,12 +245,14 @@ def bench_batched(torch, api, synth, n=1_000_000_000, npat=1024):
             "ms": round(ms, 3), "one_per_launch_ms": round(base_ms, 3),
             "method": "merged multi-pattern automata (class-compressed 16-bit tables), HIP graph replay",
             "tune": entry["tune"], "automata": int(b.plan.nautomata), "states": int(b.plan.nstates),
-            # every automaton walks the whole text: two LDS reads per step (byte class, then the
-            # 16-bit transition), against 64 two-byte reads per clock per CU (128 B/clk LDS)
+            # every automaton walks the whole text: two 2-byte LDS reads per step (byte class,
+            # then the transition), against the conflict-free 2-byte read rate measured on
+            # this GPU (the LDS's peak for such reads)
             "lds_bound": {"steps_per_s": round(n * int(b.plan.nautomata) / (ms * 1e-3), 1),
                           "lookups_per_s": round(2 * n * int(b.plan.nautomata) / (ms * 1e-3), 1),
-                          "peak_lookups_per_s": LDS_PEAK_LOOKUPS,
-                          "frac": round(2 * n * int(b.plan.nautomata) / (ms * 1e-3) / LDS_PEAK_LOOKUPS, 4)},
+                          "peak_lookups_per_s": lds_peak,
+                          "peak_source": "dfa_lds_probe: conflict-free 2-byte reads, this run",
+                          "frac": round(2 * n * int(b.plan.nautomata) / (ms * 1e-3) / lds_peak, 4)},
             "items": int(b.plan.nitems), "counts_equal_one_per_launch": equal,
             "separate_automata": {"ms": round(sep_ms, 3), "pattern_bytes_per_s": round(pb / (sep_ms * 1e-3), 1),
                                   "speedup_vs_one_per_launch": round(base_ms / sep_ms, 2),
@@ -257,6 +297,62 @@ def bench_degenerate(torch, api, d, n):
                              "kind": "oracle",
                              "sample": f"first {sn} bytes, the {len(queries)} queries job-parallel over {cores} "
                                        f"threads, {cpu_s:.1f} s on {cpu_model()}"}}
+
+
+def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0):
+    """The merged scans alone, for kernel traces and shader counters: the 1 GB x 1024-pattern
+    plan, the 18 degenerate queries over the same text and the 2000-segment plan, each run
+    `reps` times after one warm-up run, with the library's default plan (step_bytes: 1 or 2
+    forces one- or two-byte automaton steps)."""
+    t = api.tune(step_bytes=step_bytes) if step_bytes else None
+    from paper_1506_08612_amd import graph
+    out = {}
+    w = synth.many_patterns()
+    n = w.text.size
+    d = api.to_device(w.text)
+    npat = len(w.patterns)
+    jobs = [("many_patterns", api.MergedBatch([0, n], w.patterns, np.zeros(npat, np.int64), np.arange(npat), t,
+                                              device=d.device), d)]
+    rng = np.random.default_rng([6, 0x4447])  # the degenerate leg's queries
+    codes = []
+    for i in range(9):
+        c = list(synth.random_pattern(8, rng).decode())
+        c[i % 8] = "BDHV"[int(rng.integers(0, 4))]
+        codes.append("".join(c).encode())
+    codes += [synth.random_pattern(8, rng) for _ in range(9)]
+    jobs.append(("degenerate", api.DegenerateBatch([0, n], [(0, c, True) for c in codes], t, device=d.device), d))
+    ws = synth.uneven_segments()
+    dseg = api.to_device(ws.text)
+    jobs.append(("segmented", api.MergedBatch(ws.seg_off, ws.patterns, ws.pair_seg, ws.pair_pat, t,
+                                              device=dseg.device), dseg))
+    for name, b, text in jobs:
+        g = graph.GraphedBatch(text, b)
+        ms = _events_ms(torch, g.replay, reps)
+        plan = b.batch.plan if hasattr(b, "batch") else b.plan
+        out[name] = {"ms": round(ms, 4), "text_GBps": round(int(text.numel()) / ms / 1e6, 1),
+                     "automata": int(plan.nautomata), "states": int(plan.nstates), "items": int(plan.nitems),
+                     "pair_items": int(plan.pair_items), "groups": [int(x) for x in plan.group_items]}
+        log(name, out[name])
+    return out
+
+
+def bench_lds(torch, api, blocks=1024, iters=8192):
+    """LDS read rate of this GPU (dfa_lds_probe): 1- and 2-byte reads at conflict-free
+    addresses (the LDS's peak for such reads), at scattered addresses (lanes meeting in a
+    bank, as table lookups of different states do) and in chains where each address is
+    computed from the previous value (an automaton step), eight per lane.
+    1024 workgroups of 512 threads with 16 KiB of LDS each: 4 per CU, 32 waves per CU."""
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = {"cu_clocks_per_s": CU_CLOCKS_PER_S, "blocks": blocks, "iters": iters}
+    for width in (1, 2):
+        for mode in ("conflict_free", "scattered", "dependent"):
+            reads = api.lds_probe(width, mode, blocks, iters, sink)
+            ms = _events_ms(torch, lambda: api.lds_probe(width, mode, blocks, iters, sink), 5)
+            rate = reads / (ms * 1e-3)
+            out[f"u{8 * width}_{mode}"] = {
+                "ms": round(ms, 4), "reads_per_s": round(rate, 1),
+                "reads_per_clk_per_cu": round(rate / CU_CLOCKS_PER_S, 2)}
+    return out
 
 
 def bench_study(torch, api, text, dtext, pats):
@@ -425,17 +521,19 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=3_200_000_000, help="text bytes (default 3.2e9)")
     ap.add_argument("--kernel-reps", type=int, default=20, help="count-only launches timed per pattern")
-    ap.add_argument("--cpu-sample", type=int, default=400_000_000,
-                    help="text prefix (bytes) the CPU oracle scans for the baseline")
+    ap.add_argument("--cpu-sample", type=int, default=200_000_000,
+                    help="text prefix (bytes) the CPU oracle's definition (window compare) scans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run one device copy of this many bytes (counter calibration)")
     ap.add_argument("--skip-extra", action="store_true",
                     help="skip the batched, segmented and serving measurements")
     ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--study", action="store_true",
-                    help="also run the size sweep and workgroup load-balance study of the scan")
-    ap.add_argument("--only", choices=("batched", "segmented", "serving", "fasta"),
+    ap.add_argument("--merged-step", type=int, default=0, choices=(0, 1, 2),
+                    help="--only merged: bytes per automaton step (0: the library's choice)")
+    ap.add_argument("--no-study", action="store_true",
+                    help="skip the size sweep and workgroup load-balance study of the scan")
+    ap.add_argument("--only", choices=("batched", "segmented", "serving", "fasta", "lds", "merged"),
                     help="run only this leg and print its figures (for profiling)")
     a = ap.parse_args(argv)
 
@@ -457,7 +555,9 @@ def main(argv=None) -> int:
         legs = {"batched": lambda: bench_batched(torch, api, synth)[1],
                 "segmented": lambda: bench_segmented(torch, api, synth),
                 "fasta": fasta_leg,
-                "serving": lambda: bench_serving(torch, a.serve_queries)}
+                "serving": lambda: bench_serving(torch, a.serve_queries),
+                "lds": lambda: bench_lds(torch, api),
+                "merged": lambda: bench_merged_kernels(torch, api, synth, step_bytes=a.merged_step)}
         print(json.dumps({a.only: legs[a.only]()}), flush=True)
         return 0
     stream = torch.cuda.current_stream()
@@ -468,14 +568,18 @@ def main(argv=None) -> int:
     log(f"  generated in {time.time() - t0:.1f}s")
     n = w.text.size
 
-    # upload once; the text stays resident (timed separately, never inside `value`)
+    # upload once; the text stays resident (timed separately, never inside `value`).  The
+    # first copy into the new buffer also maps its pages; the same copy again from the same
+    # pinned memory into the same buffer gives the link's rate
     pinned = torch.from_numpy(w.text).pin_memory()
     dtext = torch.empty(n, dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dtext.copy_(pinned, non_blocking=True)
-    torch.cuda.synchronize()
-    h2d_s = time.perf_counter() - t0
+    h2d = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dtext.copy_(pinned, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d.append(time.perf_counter() - t0)
     del pinned
 
     pats = w.patterns
@@ -584,37 +688,41 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    # CPU baseline: the oracle on a bounded prefix, same patterns, one thread
-    cpu = None
-    parity_sample = None
+    # CPU baselines, one thread: the oracle's plain automaton scan (Alg. 1 with one worker
+    # and one lane) over the WHOLE text for each of the five patterns, count + positions in
+    # one pass; and the definition (window compare) on a prefix.  Both outputs are checked
+    # against the GPU's positions.
+    cpu = cpu_def = None
+    parity_full = parity_prefix = None
     if not a.no_cpu_baseline:
-        import oracle
+        cpu, parity_full = cpu_automaton_baseline(w.text, pats, counts, pos_bufs)
         sn = min(a.cpu_sample, n)
         sample = w.text[:sn]
         t0 = time.perf_counter()
-        oracle_pos = [oracle.occurrences(sample, p) for p in pats]
+        oracle_pos = [oracle_mod().occurrences(sample, p) for p in pats]
         cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(sn * len(pats) / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"first {sn} bytes of the text, the same {len(pats)} patterns, "
-                         f"count + positions by the definition (window compare), "
-                         f"{cpu_s:.1f} s on {cpu_model()}"}
-        # the GPU positions inside the sample must be the oracle's
+        cpu_def = {"value": round(sn * len(pats) / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": f"first {sn} bytes of the text, the same {len(pats)} patterns, "
+                             f"count + positions by the definition (window compare), "
+                             f"{cpu_s:.1f} s on {cpu_model()}"}
         ok = True
         for i, p in enumerate(pats):
             g = pos_bufs[i][:min(counts[i], caps[i])].cpu().numpy()
             g = g[g <= sn - len(p)]
             ok &= bool(np.array_equal(g, oracle_pos[i]))
-        parity_sample = ok
+        parity_prefix = ok
 
     extra = {}
-    if a.study:
+    if not a.no_study:
         extra["study"] = bench_study(torch, api, w.text, dtext, pats)
     if not a.skip_extra:
         extra["fasta"] = bench_fasta(torch, api, w.text, dtext)
         del dtext
         torch.cuda.empty_cache()
-        extra["degenerate"], extra["batched"] = bench_batched(torch, api, synth)
+        extra["lds"] = bench_lds(torch, api)
+        extra["degenerate"], extra["batched"] = bench_batched(
+            torch, api, synth, lds_peak=extra["lds"]["u16_conflict_free"]["reads_per_s"])
         torch.cuda.empty_cache()
         extra["segmented"] = bench_segmented(torch, api, synth)
         torch.cuda.empty_cache()
@@ -665,8 +773,12 @@ def main(argv=None) -> int:
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
-        "parity_sample_vs_oracle": parity_sample,
-        "h2d_GBps": round(n / h2d_s / 1e9, 2),
+        "cpu_definition_baseline": cpu_def,
+        "parity_vs_oracle_full_text": parity_full,
+        "parity_vs_oracle_definition_prefix": parity_prefix,
+        "h2d_GBps": round(n / min(h2d[1:]) / 1e9, 2),
+        "h2d_first_copy_GBps": round(n / h2d[0] / 1e9, 2),
+        "h2d_link": "PCIe, host pinned memory to HBM, one copy of the whole text (best of 2 after the first)",
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

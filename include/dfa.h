@@ -59,7 +59,9 @@ typedef struct dfa_tune {
                               * (its table, byte-class map and final-state counters);
                               * decides how many patterns share one automaton */
     int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
-    int32_t reserved[3];     /* must be zero */
+    int32_t step_bytes;      /* merged scans: text bytes per automaton step, 1 or 2 (a pair
+                              * table, where it fits automaton_bytes); other scans ignore it */
+    int32_t reserved[2];     /* must be zero */
 } dfa_tune;
 
 /* Message for the last failed call on this thread ("" if none). */
@@ -132,19 +134,24 @@ int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, in
                         int64_t *count, unsigned long long *wg_times, int64_t wg_cap,
                         const dfa_tune *tune, void *stream);
 
-/* Measurement only: the LDS gather rate of the current GPU, the ceiling of
- * the table reads every automaton step makes (Alg. 1; the sparse transition
+/* Measurement only: the LDS read rate of the current GPU, the ceiling of the
+ * table reads every automaton step makes (Alg. 1; the sparse transition
  * table of Sec. III.B, held in LDS here).  Launches `blocks` workgroups of 512
  * threads; each thread makes iters x 8 reads of `width` bytes (1 or 2) from a
- * 16 KiB LDS table, at addresses independent of the values read
- * (dependent = 0: the gather throughput) or, in 8 chains per thread, computed
- * from the chain's previous value as value x row + column (dependent = 1: an
- * automaton step's dependent read).  `sink` (device, 8 bytes, 8-byte aligned)
- * is written only in a case that does not occur; it keeps the reads.
- * Returns the number of reads launched (time the launch on `stream` to get
- * the rate), or DFA_EINVAL (width, dependent, blocks in [1, 2^20] or iters in
- * [1, 2^24] out of range, null or misaligned sink) / DFA_EHIP. */
-int64_t dfa_lds_probe(int32_t width, int32_t dependent, int32_t blocks, int64_t iters,
+ * 16 KiB LDS table, at
+ *   mode 0: scattered addresses independent of the values read (the gather
+ *           rate when lanes of a wave meet in the same bank),
+ *   mode 1: addresses computed, in 8 chains per thread, from the chain's
+ *           previous value as value x row + column (an automaton step's
+ *           dependent read),
+ *   mode 2: addresses where lane l of each half-wave reads dword l of a row
+ *           (no two lanes of a half-wave in one bank: the conflict-free rate).
+ * `sink` (device, 8 bytes, 8-byte aligned) is written only in a case that
+ * does not occur; it keeps the reads.  Returns the number of reads launched
+ * (time the launch on `stream` to get the rate), or DFA_EINVAL (width, mode,
+ * blocks in [1, 2^20] or iters in [1, 2^24] out of range, null or misaligned
+ * sink) / DFA_EHIP. */
+int64_t dfa_lds_probe(int32_t width, int32_t mode, int32_t blocks, int64_t iters,
                       unsigned long long *sink, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -253,6 +260,7 @@ int64_t dfa_ac_build(const uint8_t *patterns, const int64_t *pat_off, const int3
                      int32_t npat, uint16_t *table, int64_t max_states, int32_t *first_final,
                      int32_t *out_off, int32_t *out_pat, int64_t out_cap, int64_t *n_out);
 
+#define DFA_MERGED_GROUPS 4
 typedef struct dfa_merged_plan {
     int64_t nitems;          /* work items: (tile of a segment, merged automaton) */
     int64_t nautomata;       /* merged automata built */
@@ -267,8 +275,14 @@ typedef struct dfa_merged_plan {
     int64_t entries_offset;
     int64_t visits_offset;
     int32_t waves_per_group; /* 64-lane waves per workgroup */
-    int32_t lds_bytes;       /* dynamic LDS of the scan launch */
+    int32_t lds_bytes;       /* dynamic LDS of the largest scan launch */
     int32_t reserved[4];
+    /* the scan's launches, in order: group g runs the next group_items[g]
+     * work items with group_lds[g] bytes of LDS, over pair automata (two
+     * text bytes per step) if group_pair[g] != 0 */
+    int64_t group_items[DFA_MERGED_GROUPS];
+    int32_t group_lds[DFA_MERGED_GROUPS];
+    int32_t group_pair[DFA_MERGED_GROUPS];
 } dfa_merged_plan;
 
 /* Batched counting with merged automata: same question as the dfa_batch_*

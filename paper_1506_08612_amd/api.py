@@ -25,6 +25,7 @@ DFA_EINVAL = -1
 DFA_EHIP = -2
 DFA_ENOSPACE = -3
 MAX_M = 255
+MERGED_GROUPS = 4  # DFA_MERGED_GROUPS
 NOALLOC_SCRATCH_BYTES = 64 << 20  # DFA_NOALLOC_SCRATCH_BYTES
 ALPHABET = 256
 
@@ -44,7 +45,8 @@ class Tune(ctypes.Structure):
         ("dfas_per_group", ctypes.c_int32),
         ("automaton_bytes", ctypes.c_int32),
         ("line_bytes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("step_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -82,7 +84,15 @@ class MergedPlan(ctypes.Structure):
         ("waves_per_group", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 4),
+        ("group_items", ctypes.c_int64 * MERGED_GROUPS),
+        ("group_lds", ctypes.c_int32 * MERGED_GROUPS),
+        ("group_pair", ctypes.c_int32 * MERGED_GROUPS),
     ]
+
+    @property
+    def pair_items(self) -> int:
+        """Work items walked two bytes per step (pair automata)."""
+        return sum(int(self.group_items[g]) for g in range(MERGED_GROUPS) if self.group_pair[g])
 
 
 _i64 = ctypes.c_int64
@@ -144,9 +154,9 @@ def _check(rc: int) -> int:
 
 
 def tune(chain_bytes: int = 0, waves_per_group: int = 0, chains_per_lane: int = 0,
-         dfas_per_group: int = 0, automaton_bytes: int = 0, line_bytes: int = 0) -> Tune:
+         dfas_per_group: int = 0, automaton_bytes: int = 0, line_bytes: int = 0, step_bytes: int = 0) -> Tune:
     return Tune(chain_bytes, waves_per_group, chains_per_lane, dfas_per_group, automaton_bytes,
-                line_bytes)
+                line_bytes, step_bytes)
 
 
 def _tune_ptr(t: Optional[Tune]):
@@ -290,9 +300,13 @@ def count_timed(text, table, m: int, t: Optional[Tune] = None, stream=None, wg_c
         return int(out.item()), times[:3 * k].view(k, 3).cpu().numpy()
 
 
-def lds_probe(width: int, dependent: bool, blocks: int, iters: int, sink, stream=None) -> int:
-    """Enqueue the LDS gather probe; returns the number of reads it makes."""
-    return _check(lib.dfa_lds_probe(int(width), int(bool(dependent)), int(blocks), int(iters),
+LDS_PROBE_MODES = {"scattered": 0, "dependent": 1, "conflict_free": 2}
+
+
+def lds_probe(width: int, mode: str, blocks: int, iters: int, sink, stream=None) -> int:
+    """Enqueue the LDS read probe (mode: scattered, dependent or conflict_free); returns the
+    number of reads it makes."""
+    return _check(lib.dfa_lds_probe(int(width), LDS_PROBE_MODES[mode], int(blocks), int(iters),
                                     _ptr(sink, "int64", "sink", 1), _stream_handle(stream)))
 
 

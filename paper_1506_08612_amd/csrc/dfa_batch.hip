@@ -257,11 +257,15 @@ int plan_batch(const int64_t *seg_off, int32_t nseg, const int64_t *table_off, c
         return DFA_EINVAL;
     }
     if (t) {
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 2; ++i)
             if (t->reserved[i]) {
                 dfa::set_error("tune.reserved must be zero");
                 return DFA_EINVAL;
             }
+        if (t->step_bytes < 0 || t->step_bytes > 2) {
+            dfa::set_error("tune.step_bytes=%d must be 1 or 2 (or 0)", t->step_bytes);
+            return DFA_EINVAL;
+        }
         if (t->dfas_per_group && t->dfas_per_group != 2 && t->dfas_per_group != 4 && t->dfas_per_group != 8 &&
             t->dfas_per_group != 16) {
             dfa::set_error("tune.dfas_per_group=%d must be 2, 4, 8 or 16 (or 0)", t->dfas_per_group);

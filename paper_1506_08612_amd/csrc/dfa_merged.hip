@@ -18,6 +18,16 @@
 // an LDS histogram and turned into per-pair counts at the end through the
 // per-state output lists.
 //
+// Pair automata.  Where an automaton has few byte classes (DNA patterns have
+// five: A, C, G, T and everything else) its table over PAIRS of classes, the
+// state after two bytes, takes ncls^2 columns per state; small automata (one
+// segment's patterns, a set of degenerate k-mers) fit LDS that way, and a
+// full wave's rounds then take one dependent table read per two bytes instead
+// of two per byte: the transition reads, whose lanes meet in LDS banks, are
+// the scan's bottleneck.  A pair entry carries one more bit: whether the state
+// after the first byte reports, so that visits stay exact (the rare pair with
+// one recomputes that state with the one-step table).
+//
 // Ownership.  A walk owns the match starts of its span [w, w + S) and reads
 // max(m) - 1 bytes past it (clipped at the segment end).  A match that ends
 // inside the span starts inside it (the walk starts in the start state at w);
@@ -62,14 +72,23 @@ constexpr int kCmapBytes = 512;                  // 256 x u16: twice the class o
 
 typedef __attribute__((address_space(3))) const uint16_t lds_u16;
 
+// An automaton's LDS image (copied from the workspace to LDS address 0; its
+// visit counters follow it).  One-step automata: the nstates x ncls u16 table
+// at 0, then the 16-bit class map.  Pair automata (kPairMaps): two byte maps
+// at 0 and 256 (the first byte of a pair gives 2 ncls c, the second 2 c), the
+// nstates x ncls^2 u16 pair table at kPairMaps, the one-step table, then the
+// 16-bit class map, whose entries hold the one-step table's LDS offset plus
+// 2 c, so that one-step reads need no base either.
 struct MAuto {
-    int64_t table_off;  // offset in the workspace: nstates x ncls u16 table (padded to 16 bytes), then the class map
+    int64_t table_off;  // offset of the image in the workspace
     int64_t fin_base;   // global index of this automaton's first reporting state
     int32_t nstates;
     int32_t first_final;
     int32_t ncls;
     int32_t maxm;
-    int32_t table_bytes;  // padded table bytes (the class map follows)
+    int32_t image_bytes;  // bytes of the image (16-byte multiple)
+    int32_t cmap_off;     // LDS offset of the 16-bit class map
+    int32_t pair;         // nonzero: pair automaton
     int32_t pad;
 };
 
@@ -105,12 +124,22 @@ struct MLane {
 };
 
 struct MCtx {
-    uint32_t row2;   // bytes per table row
-    uint32_t cmap;   // LDS address of the class map
+    uint32_t row2;   // bytes per one-step table row
+    uint32_t rowp;   // bytes per pair table row (pair automata)
+    uint32_t cmap;   // LDS address of the 16-bit class map
     uint32_t hist;   // LDS address of the visit counters
     uint32_t F;      // first reporting state
     int64_t fin_base;
 };
+
+// Pair automata: the byte maps sit at LDS 0 and 256 and the pair table at
+// kPairMaps, so every address of a pair step is a sum of per-lane terms and a
+// constant the reads take as their offset.  A pair entry is the state after
+// both bytes, with bit 15 set when the state after the first byte reports
+// (states stay below 2^15).
+constexpr uint32_t kPairMaps = 512;
+constexpr uint32_t kMidReports = 0x8000u;
+typedef __attribute__((address_space(3))) const uint8_t lds_u8c;
 
 // One automaton step: class of byte c (the map holds twice the class), then
 // the next state.
@@ -169,9 +198,47 @@ __device__ __forceinline__ void mwalk16(const v4u &t, uint32_t &q, uint32_t jb, 
     }
 }
 
+// A pair whose entry e is at least F (a reporting state after its second
+// byte, or bit 15: after its first) counts its visits; qp is the state before
+// the pair and c1 its first byte.
+__device__ __forceinline__ void pair_visits(uint32_t e, uint32_t qp, uint32_t c1, const MCtx &x, uint32_t *hist) {
+    if (e & kMidReports) {
+        const uint32_t k2 = *reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * c1));
+        const uint32_t mid = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(qp, x.row2) + k2));
+        atomicAdd(hist + (mid - x.F), 1u);
+    }
+    const uint32_t q = e & (kMidReports - 1u);
+    if (q >= x.F) atomicAdd(hist + (q - x.F), 1u);
+}
+
+// Walk 16 bytes of a full wave two bytes per step with a pair automaton: per
+// text word (4 bytes), the byte maps of its bytes, then 2 dependent pair
+// reads, then one test of the larger entry against F (reporting states are
+// numbered last, and bit 15 exceeds every state).
+__device__ __forceinline__ void mwalk16_pair(const v4u &t, uint32_t &q, const MCtx &x, unsigned char *smem) {
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
+#pragma unroll
+    for (int wd = 0; wd < 4; ++wd) {
+        const uint32_t w = t[wd];
+        const uint32_t a0 = *reinterpret_cast<lds_u8c *>(uintptr_t(w & 0xffu));
+        const uint32_t b0 = *reinterpret_cast<lds_u8c *>(uintptr_t(256u + ((w >> 8) & 0xffu)));
+        const uint32_t a1 = *reinterpret_cast<lds_u8c *>(uintptr_t((w >> 16) & 0xffu));
+        const uint32_t b1 = *reinterpret_cast<lds_u8c *>(uintptr_t(256u + (w >> 24)));
+        const uint32_t q0 = q;
+        const uint32_t e0 = *reinterpret_cast<lds_u16 *>(uintptr_t(kPairMaps + __umul24(q, x.rowp) + a0 + b0));
+        const uint32_t q1 = e0 & (kMidReports - 1u);
+        const uint32_t e1 = *reinterpret_cast<lds_u16 *>(uintptr_t(kPairMaps + __umul24(q1, x.rowp) + a1 + b1));
+        q = e1 & (kMidReports - 1u);
+        if (max(e0, e1) >= x.F) {
+            if (e0 >= x.F) pair_visits(e0, q0, w & 0xffu, x, hist);
+            if (e1 >= x.F) pair_visits(e1, q1, (w >> 16) & 0xffu, x, hist);
+        }
+    }
+}
+
 // The four units of a staged round, the next one read from LDS while the
 // current one is walked.
-template <bool GUARD>
+template <bool GUARD, bool PAIR = false>
 __device__ __forceinline__ void mwalk_round(const v4u *xb, int lane, uint32_t &q, uint32_t rb, const MCtx &x,
                                             const MLane &L, unsigned char *smem, const MParams &p) {
     using G = Geo<kLine>;
@@ -179,37 +246,87 @@ __device__ __forceinline__ void mwalk_round(const v4u *xb, int lane, uint32_t &q
 #pragma unroll
     for (int u = 0; u < G::U; ++u) {
         if (u + 1 < G::U) nxt = unit_of<kLine>(xb, 0, lane, u + 1);
-        mwalk16<GUARD>(cur, q, rb + 16u * u, x, L, smem, p);
+        if (PAIR)
+            mwalk16_pair(cur, q, x, smem);
+        else
+            mwalk16<GUARD>(cur, q, rb + 16u * u, x, L, smem, p);
         cur = nxt;
     }
 }
 
-template <int H>
-__global__ __launch_bounds__(512) void k_merged(MParams p) {
+// The rounds and overlap of a full wave (every walk inside its segment, its
+// span owned and its overlap inside the segment and the text).  S is a
+// multiple of 128: R is even and every round is whole.  PAIR: the rounds go
+// two bytes per step; the overlap always goes one byte per step (it counts
+// only matches that start inside the span).
+template <int H, bool PAIR>
+__device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, int64_t wbase, int64_t wstart, int64_t S,
+                                          uint32_t lane_off, int maxm, uint32_t &q, const MCtx &x, const MLane &L,
+                                          unsigned char *smem) {
+    using G = Geo<kLine>;
+    const int R = int(S / kLine);
+    const int rlast = R - 1;
+    const uint32_t off_none = 16u * uint32_t(lane % G::U);
+    const int hu = (maxm - 1 + 15) / 16;
+    v4u pa[1][G::U], pb[1][G::U], halo[1][H];
+    fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 0, rlast);
+    fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 1, rlast);
+    stage_round<1, kLine>(pa, xb, lane);
+    grab_halo<1, kLine, H>(halo, xb, lane, p.text, wbase, S, hu, G::U);
+    mwalk_round<false, PAIR>(xb, lane, q, 0u, x, L, smem, p);
+    stage_round<1, kLine>(pb, xb, lane);
+    fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 2, rlast);
+    fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 3, rlast);
+    mwalk_round<false, PAIR>(xb, lane, q, uint32_t(kLine), x, L, smem, p);
+    for (int r = 2; r < R; r += 2) {
+        stage_round<1, kLine>(pa, xb, lane);
+        mwalk_round<false, PAIR>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
+        stage_round<1, kLine>(pb, xb, lane);
+        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, r + 2, rlast);
+        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
+        mwalk_round<false, PAIR>(xb, lane, q, uint32_t((r + 1) * kLine), x, L, smem, p);
+    }
+    // the overlap: its first H units from registers, the rest from memory
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+        if (u < hu) mwalk16<true>(halo[0][u], q, uint32_t(S) + 16u * u, x, L, smem, p);
+    for (int u = H; u < hu; ++u) {
+        const v4u t = *reinterpret_cast<const v4u *>(p.text + wstart + S + 16 * u);
+        mwalk16<true>(t, q, uint32_t(S) + 16u * u, x, L, smem, p);
+    }
+}
+
+// PAIR: every item's automaton is a pair automaton (the plan puts those items
+// first and launches them apart, so that each kernel keeps only its own path's
+// registers).
+template <int H, bool PAIR>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_merged(MParams p) {
     using G = Geo<kLine>;
     extern __shared__ __align__(16) unsigned char smem[];
     const MItem it = p.items[blockIdx.x];
     const MAuto au = p.autos[it.automaton];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-    const uint32_t tb = uint32_t(__builtin_amdgcn_readfirstlane(au.table_bytes));
+    const uint32_t ib = uint32_t(__builtin_amdgcn_readfirstlane(au.image_bytes));
     const uint32_t F = uint32_t(__builtin_amdgcn_readfirstlane(au.first_final));
     const uint32_t nst = uint32_t(__builtin_amdgcn_readfirstlane(au.nstates));
+    const uint32_t ncls = uint32_t(__builtin_amdgcn_readfirstlane(au.ncls));
     const uint32_t nfin = nst - F;
     const int maxm = __builtin_amdgcn_readfirstlane(au.maxm);
 
-    // LDS: table (from address 0), class map, visit counters, transpose buffers
+    // LDS: the automaton's image (from address 0), visit counters, transpose buffers
     MCtx x;
-    x.row2 = 2u * uint32_t(__builtin_amdgcn_readfirstlane(au.ncls));
-    x.cmap = tb;
-    x.hist = tb + kCmapBytes;
+    x.row2 = 2u * ncls;
+    x.rowp = 2u * ncls * ncls;
+    x.cmap = uint32_t(__builtin_amdgcn_readfirstlane(au.cmap_off));
+    x.hist = ib;
     x.F = F;
     x.fin_base = au.fin_base;
     const uint32_t stage = (x.hist + 4u * nfin + 15u) & ~15u;
     v4u *xb = reinterpret_cast<v4u *>(smem + stage + wave * (kWave * kLine));
     {
         const v4u *src = reinterpret_cast<const v4u *>(p.ws + au.table_off);
-        const uint32_t chunks = (tb + kCmapBytes) / 16u;
+        const uint32_t chunks = ib / 16u;
         for (uint32_t i = threadIdx.x; i < chunks; i += blockDim.x) reinterpret_cast<v4u *>(smem)[i] = src[i];
         uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
         for (uint32_t i = threadIdx.x; i < nfin; i += blockDim.x) hist[i] = 0;
@@ -241,37 +358,7 @@ __global__ __launch_bounds__(512) void k_merged(MParams p) {
                       wlast + int64_t(rounds_all) * kLine <= p.n;
 
     if (full) {
-        // S is a multiple of 128: R is even and every round is whole
-        const int R = int(S / kLine);
-        const int rlast = R - 1;
-        const uint32_t off_none = 16u * uint32_t(lane % G::U);
-        const int hu = (maxm - 1 + 15) / 16;
-        v4u pa[1][G::U], pb[1][G::U], halo[1][H];
-        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 0, rlast);
-        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 1, rlast);
-        stage_round<1, kLine>(pa, xb, lane);
-        grab_halo<1, kLine, H>(halo, xb, lane, p.text, wbase, S, hu, G::U);
-        mwalk_round<false>(xb, lane, q, 0u, x, L, smem, p);
-        stage_round<1, kLine>(pb, xb, lane);
-        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 2, rlast);
-        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 3, rlast);
-        mwalk_round<false>(xb, lane, q, uint32_t(kLine), x, L, smem, p);
-        for (int r = 2; r < R; r += 2) {
-            stage_round<1, kLine>(pa, xb, lane);
-            mwalk_round<false>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
-            stage_round<1, kLine>(pb, xb, lane);
-            fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, r + 2, rlast);
-            fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
-            mwalk_round<false>(xb, lane, q, uint32_t((r + 1) * kLine), x, L, smem, p);
-        }
-        // the overlap: its first H units from registers, the rest from memory
-#pragma unroll
-        for (int u = 0; u < H; ++u)
-            if (u < hu) mwalk16<true>(halo[0][u], q, uint32_t(S) + 16u * u, x, L, smem, p);
-        for (int u = H; u < hu; ++u) {
-            const v4u t = *reinterpret_cast<const v4u *>(p.text + wstart + S + 16 * u);
-            mwalk16<true>(t, q, uint32_t(S) + 16u * u, x, L, smem, p);
-        }
+        walk_full<H, PAIR>(p, xb, lane, wbase, wstart, S, lane_off, maxm, q, x, L, smem);
     } else {
         // edge waves: the segment's first or last walks, or the text's end
         v4u pf[1][G::U];
@@ -319,9 +406,11 @@ __global__ void k_visits_to_counts(const unsigned long long *visits, const int32
 
 using dfa::hip_ok;
 
-const void *merged_fn(int H) {
-    if (H == 1) return reinterpret_cast<const void *>(&k_merged<1>);
-    return reinterpret_cast<const void *>(&k_merged<4>);
+const void *merged_fn(int H, bool pair) {
+    if (H == 1) return pair ? reinterpret_cast<const void *>(&k_merged<1, true>)
+                            : reinterpret_cast<const void *>(&k_merged<1, false>);
+    return pair ? reinterpret_cast<const void *>(&k_merged<4, true>)
+                : reinterpret_cast<const void *>(&k_merged<4, false>);
 }
 
 struct MHostPlan {
@@ -332,16 +421,42 @@ struct MHostPlan {
     std::vector<uint8_t> area;  // tables and class maps
     int waves = kDefaultWaves;
     int H = 1;
-    int lds = 0;
+    int lds = 0;  // dynamic LDS of the largest launch
+    // launch groups (pair automata needing at most a third, a half, all of a
+    // CU's LDS per workgroup; then one-step automata): items and LDS of each
+    int64_t group_items[DFA_MERGED_GROUPS] = {};
+    int group_lds[DFA_MERGED_GROUPS] = {};
     int64_t text_bytes = 0;
     int64_t nstates = 0;
     int64_t ncounts = 0;
     const int32_t *pair_dst = nullptr;  // counter of each pair (null: the pair itself)
+    bool allow_pair = true;             // pair automata where they fit the budget
+    bool pack_pairs = false;            // pack patterns so that automata fit the budget as pair automata
+    int budget = kDefaultAutomatonBytes;
 };
 
+// Pair automata: at most kPairMaxCls byte classes (the first byte's map entry,
+// 2 ncls c, must fit a byte), states below 2^15, every image offset below 64
+// KiB (the 16-bit class map holds the one-step table's offset).
+constexpr int kPairMaxCls = 11;
+
 int64_t auto_lds_bytes(const MAuto &a) {
-    return a.table_bytes + kCmapBytes + dfa::round_up(int64_t(a.nstates - a.first_final) * 4, 16);
+    return a.image_bytes + dfa::round_up(int64_t(a.nstates - a.first_final) * 4, 16);
 }
+
+// LDS is handed to workgroups in blocks; counted in whole kLdsBlock units so
+// that a third of the CU's LDS really fits three workgroups.
+constexpr int64_t kLdsBlock = 2048;
+
+// Workgroups that fit a CU when each needs `need` bytes of LDS (by LDS, and
+// by registers: the kernels keep 6 waves per SIMD, 24 per CU).
+int64_t groups_for(int64_t need, int waves) {
+    const int64_t by_lds = kLdsPerCu / dfa::round_up(need, kLdsBlock);
+    return std::max<int64_t>(1, std::min<int64_t>(by_lds, 24 / waves));
+}
+
+// ... with an automaton of `bytes` plus one transpose buffer per wave
+int64_t groups_per_cu(int64_t bytes, int waves) { return groups_for(bytes + int64_t(waves) * kWave * kLine, waves); }
 
 int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const uint8_t *patterns,
                   const int64_t *pat_off, const int32_t *pat_len, MHostPlan &hp) {
@@ -364,14 +479,55 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     m.first_final = a.first_final;
     m.ncls = a.ncls;
     m.maxm = maxm;
-    m.table_bytes = int32_t(dfa::round_up(int64_t(a.nstates) * a.ncls * 2, 16));
     m.table_off = int64_t(hp.area.size());
     m.fin_base = int64_t(hp.out_off.size()) - 1;
-    hp.area.resize(hp.area.size() + size_t(m.table_bytes + kCmapBytes), 0);
-    uint16_t *tab = reinterpret_cast<uint16_t *>(hp.area.data() + m.table_off);
+    const int64_t ns = a.nstates, nc = a.ncls;
+    const int64_t one = dfa::round_up(ns * nc * 2, 16);      // one-step table
+    const int64_t pairs = dfa::round_up(ns * nc * nc * 2, 16);  // pair table
+    const int64_t hist = dfa::round_up((ns - a.first_final) * 4, 16);
+    const int64_t pair_image = int64_t(kPairMaps) + pairs + one + kCmapBytes;
+    const bool pair_ok = hp.allow_pair && nc <= kPairMaxCls && ns < int64_t(kMidReports) &&
+                         pair_image + hist <= hp.budget && pair_image <= 65536;
+    // A pair automaton halves the dependent table reads per byte of a full
+    // wave's rounds, but its larger image may leave room for fewer workgroups
+    // per CU.  Measured (segments of 1 kB - 250 MB with 1-16 patterns of 6-48
+    // bytes, and 72 8-mers over 1 GB): at equal workgroups per CU a pair
+    // automaton walks a segment ~15 % faster; with one workgroup fewer it is
+    // slower, except where the patterns are short (up to 17 bytes: the overlap
+    // walked one byte per step is short too), where two pair workgroups beat
+    // three one-step ones by ~7 %.  Taken on that evidence, or always when the
+    // plan packs for pairs.
+    const int64_t one_image = one + kCmapBytes;
+    const int64_t g_pair = groups_per_cu(pair_image + hist, hp.waves);
+    const int64_t g_one = groups_per_cu(one_image + hist, hp.waves);
+    m.pair = pair_ok && (hp.pack_pairs || g_pair >= g_one || (maxm <= 17 && g_pair >= 2 && g_pair + 1 >= g_one));
+    const int64_t tab1 = m.pair ? int64_t(kPairMaps) + pairs : 0;  // LDS offset of the one-step table
+    m.cmap_off = int32_t(tab1 + one);
+    m.image_bytes = int32_t(tab1 + one + kCmapBytes);
+    hp.area.resize(hp.area.size() + size_t(m.image_bytes), 0);
+    uint8_t *img = hp.area.data() + m.table_off;
+    uint16_t *tab = reinterpret_cast<uint16_t *>(img + tab1);
     for (size_t i = 0; i < a.next.size(); ++i) tab[i] = uint16_t(a.next[i]);
-    uint16_t *cm = reinterpret_cast<uint16_t *>(hp.area.data() + m.table_off + m.table_bytes);
-    for (int b = 0; b < 256; ++b) cm[b] = uint16_t(2 * a.cls[b]);
+    uint16_t *cm = reinterpret_cast<uint16_t *>(img + m.cmap_off);
+    for (int b = 0; b < 256; ++b) cm[b] = uint16_t(tab1 + 2 * a.cls[b]);
+    if (m.pair) {
+        // byte maps: 2 ncls c for a pair's first byte, 2 c for its second; entry
+        // (q, c1 c2) = the state after both bytes, bit 15 if the one after c1 reports
+        for (int b = 0; b < 256; ++b) {
+            img[b] = uint8_t(2 * nc * a.cls[b]);
+            img[256 + b] = uint8_t(2 * a.cls[b]);
+        }
+        uint16_t *pt = reinterpret_cast<uint16_t *>(img + kPairMaps);
+        for (int64_t q = 0; q < ns; ++q)
+            for (int64_t c1 = 0; c1 < nc; ++c1) {
+                const int32_t mid = a.next[size_t(q * nc + c1)];
+                for (int64_t c2 = 0; c2 < nc; ++c2) {
+                    const int32_t end = a.next[size_t(int64_t(mid) * nc + c2)];
+                    pt[q * nc * nc + c1 * nc + c2] =
+                        uint16_t(end | (mid >= a.first_final ? int32_t(kMidReports) : 0));
+                }
+            }
+    }
     for (int32_t f = 0; f < a.nstates - a.first_final; ++f) {
         for (int32_t e = a.out_off[size_t(f)]; e < a.out_off[size_t(f) + 1]; ++e) {
             const int64_t k = ks[size_t(a.out_pat[size_t(e)])];
@@ -419,11 +575,17 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
     int budget = kDefaultAutomatonBytes;
     int64_t fixed_span = 0;
     if (t) {
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 2; ++i)
             if (t->reserved[i]) {
                 dfa::set_error("tune.reserved must be zero");
                 return DFA_EINVAL;
             }
+        if (t->step_bytes < 0 || t->step_bytes > 2) {
+            dfa::set_error("tune.step_bytes=%d must be 1 or 2 (or 0)", t->step_bytes);
+            return DFA_EINVAL;
+        }
+        if (t->step_bytes == 1) hp.allow_pair = false;
+        if (t->step_bytes == 2) hp.pack_pairs = true;
         if (t->waves_per_group < 0 || t->waves_per_group > 8) {
             dfa::set_error("tune.waves_per_group=%d outside [1, 8]", t->waves_per_group);
             return DFA_EINVAL;
@@ -439,6 +601,7 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         }
         if (t->waves_per_group) hp.waves = t->waves_per_group;
         if (t->automaton_bytes) budget = t->automaton_bytes;
+        hp.budget = budget;
         fixed_span = t->chain_bytes;
     }
     for (int32_t s = 0; s < nseg; ++s)
@@ -490,7 +653,11 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         for (int b = 0; b < 256; ++b) ncls += used[b];
         // add patterns while the trie (counted incrementally from the common
         // prefix with the previous pattern) fits the budget
-        const int64_t per_state = 2 * ncls + 4;
+        // LDS per state: one-step table row and visit counter, and with pair
+        // packing the pair table row too (plus the two byte maps per automaton)
+        const bool pp = hp.pack_pairs && ncls <= kPairMaxCls;
+        const int64_t per_state = 2 * ncls + 4 + (pp ? 2 * ncls * ncls : 0);
+        const int64_t fixed = kCmapBytes + (pp ? int64_t(kPairMaps) : 0);
         const size_t a_first = hp.autos.size();
         std::vector<int64_t> cur;
         int64_t states = 1;
@@ -504,7 +671,7 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
                 while (common < n && patterns[pat_off[j] + common] == patterns[pat_off[jp] + common]) ++common;
             }
             const int64_t add = pat_len[j] - common;
-            if (!cur.empty() && ((states + add) * per_state + kCmapBytes > budget || states + add > DFA_AC_MAX_STATES)) {
+            if (!cur.empty() && ((states + add) * per_state + fixed > budget || states + add > DFA_AC_MAX_STATES)) {
                 const int rc = add_automaton(cur, pair_pat, patterns, pat_off, pat_len, hp);
                 if (rc != DFA_OK) return rc;
                 cur.clear();
@@ -520,8 +687,11 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         seg_autos.emplace_back(a_first, hp.autos.size());
     }
     hp.H = maxm_all <= 17 ? 1 : 4;
-    int64_t auto_max = 0;
-    for (const MAuto &a : hp.autos) auto_max = std::max(auto_max, auto_lds_bytes(a));
+    int64_t auto_max = 0, one_max = 0, pair_max = 0;
+    for (const MAuto &a : hp.autos) {
+        auto_max = std::max(auto_max, auto_lds_bytes(a));
+        (a.pair ? pair_max : one_max) = std::max(a.pair ? pair_max : one_max, auto_lds_bytes(a));
+    }
     // fewer waves per workgroup if the largest automaton leaves too little room
     while (hp.waves > 1 && auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) --hp.waves;
     if (auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) {
@@ -564,7 +734,26 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         dfa::set_error("dfa_merged: too many work items");
         return DFA_EINVAL;
     }
-    hp.lds = int(auto_max + int64_t(hp.waves) * kWave * kLine);
+    // launch groups, each with the LDS its largest automaton needs: pair
+    // automata by how many workgroups per CU they leave room for (3, 2, 1),
+    // then the one-step ones; items keep their order inside a group
+    const int64_t staging = int64_t(hp.waves) * kWave * kLine;
+    auto group_of = [&](const MItem &it) {
+        const MAuto &a = hp.autos[size_t(it.automaton)];
+        if (!a.pair) return DFA_MERGED_GROUPS - 1;
+        const int64_t g = groups_for(auto_lds_bytes(a) + staging, hp.waves);
+        return g >= 3 ? 0 : g == 2 ? 1 : 2;
+    };
+    std::stable_sort(hp.items.begin(), hp.items.end(),
+                     [&](const MItem &x, const MItem &y) { return group_of(x) < group_of(y); });
+    for (const MItem &it : hp.items) {
+        const int g = group_of(it);
+        hp.group_items[g] += 1;
+        hp.group_lds[g] = std::max(hp.group_lds[g], int(auto_lds_bytes(hp.autos[size_t(it.automaton)]) + staging));
+    }
+    hp.lds = int(auto_max + staging);
+    (void)one_max;
+    (void)pair_max;
     return DFA_OK;
 }
 
@@ -620,6 +809,11 @@ extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const ui
     plan->waves_per_group = hp.waves;
     plan->lds_bytes = hp.lds;
     plan->reserved[0] = hp.H;
+    for (int g = 0; g < DFA_MERGED_GROUPS; ++g) {
+        plan->group_items[g] = hp.group_items[g];
+        plan->group_lds[g] = hp.group_lds[g];
+        plan->group_pair[g] = g < DFA_MERGED_GROUPS - 1 ? 1 : 0;
+    }
     if (!workspace) {
         dfa::clear_error();
         return DFA_OK;  // size query
@@ -669,8 +863,14 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
         return DFA_EINVAL;
     }
     const int H = plan->reserved[0];
+    int64_t grouped = 0;
+    bool groups_ok = true;
+    for (int g = 0; g < DFA_MERGED_GROUPS; ++g) {
+        groups_ok &= plan->group_items[g] >= 0 && plan->group_lds[g] >= 0 && plan->group_lds[g] <= kLdsPerCu;
+        grouped += plan->group_items[g];
+    }
     if ((H != 1 && H != 4) || plan->waves_per_group < 1 || plan->waves_per_group > 8 || plan->lds_bytes < 0 ||
-        plan->lds_bytes > kLdsPerCu) {
+        plan->lds_bytes > kLdsPerCu || !groups_ok || grouped != plan->nitems) {
         dfa::set_error("dfa_merged_run: plan not made by dfa_merged_prepare");
         return DFA_EINVAL;
     }
@@ -688,8 +888,6 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
         dfa::clear_error();
         return DFA_OK;
     }
-    const void *fn = merged_fn(H);
-    if (!dfa::allow_lds(fn, kLdsPerCu)) return DFA_EHIP;
     MParams mp{};
     mp.text = text;
     mp.n = n;
@@ -700,11 +898,20 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
     mp.out_ent = reinterpret_cast<const OutEntry *>(ws + plan->entries_offset);
     mp.visits = visits;
     mp.counts = cnt;
-    void *args[] = {&mp};
-    if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(plan->nitems)), dim3(plan->waves_per_group * kWave), args,
-                                size_t(plan->lds_bytes), st),
-                "k_merged launch"))
-        return DFA_EHIP;
+    // one launch per group of items
+    for (int64_t g = 0, first = 0; g < DFA_MERGED_GROUPS; first += plan->group_items[g], ++g) {
+        const int64_t count = plan->group_items[g];
+        if (count == 0) continue;
+        const void *fn = merged_fn(H, plan->group_pair[g] != 0);
+        if (!dfa::allow_lds(fn, kLdsPerCu)) return DFA_EHIP;
+        MParams kp = mp;
+        kp.items = mp.items + first;
+        void *args[] = {&kp};
+        if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(count)), dim3(plan->waves_per_group * kWave), args,
+                                    size_t(plan->group_lds[g]), st),
+                    "k_merged launch"))
+            return DFA_EHIP;
+    }
     if (plan->nfinal > 0) {
         const int64_t want = dfa::ceil_div(plan->nfinal, 256);
         hipLaunchKernelGGL(k_visits_to_counts, dim3(unsigned(std::min<int64_t>(want, 4096))), dim3(256), 0, st, visits,

@@ -1,15 +1,20 @@
-// LDS gather rate of the device (measurement only).
+// LDS read rate of the device (measurement only).
 //
 // Every automaton step of the paper's scan is one table read at an address
 // that depends on the state and the text byte (Alg. 1; the sparse transition
 // table of Sec. III.B).  On gfx950 the tables live in LDS, so the rate at
 // which LDS serves single-byte and two-byte reads at scattered addresses is
 // the ceiling of every table-bound scan here (the merged multi-pattern scan
-// above all).  This kernel measures that rate two ways:
+// above all).  This kernel measures that rate three ways (the C ABI's mode
+// 0, 1 and 2 are scattered, dependent and conflict-free):
 //
-//   independent  eight reads per lane and iteration at addresses that do not
+//   scattered    eight reads per lane and iteration at addresses that do not
 //                depend on the values read (a lane's base plus fixed
-//                offsets): the gather throughput;
+//                offsets): the gather throughput at scattered addresses,
+//                where lanes of a wave meet in the same bank;
+//   conflict-free  the same, but lane l of each half-wave reads dword l of a
+//                128-byte row, so that no two lanes of a half-wave share a
+//                bank: the conflict-free read rate;
 //   dependent    eight chains per lane, each read's address computed from the
 //                previous value of its chain as an automaton step computes
 //                the next row from the state (value x row + column): the
@@ -54,7 +59,9 @@ __device__ __forceinline__ uint32_t lds_read(uint32_t addr) {
     return *reinterpret_cast<lds16 *>(uintptr_t(addr));
 }
 
-template <int WIDTH, bool DEP>
+enum ProbeMode { kIndependent = 0, kDependent = 1, kLinear = 2 };
+
+template <int WIDTH, int MODE>
 __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsigned long long *sink) {
     extern __shared__ __align__(16) unsigned char smem[];
     // values below 128: one byte each, or the low byte of each 16-bit entry
@@ -64,7 +71,16 @@ __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsi
     __syncthreads();
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
-    if (!DEP) {
+    if (MODE == kLinear) {
+        // lane l of a half-wave: byte 4 (l % 32) of a row; rows move by whole 128-byte
+        // steps (base < 8 KiB, offsets 7 x 1024 at most: every address < 16 KiB)
+        uint32_t base = 4u * (threadIdx.x & 31u) + (mix(tid >> 6) & 63u) * 128u;
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int c = 0; c < kReadsPerIter; ++c) acc += lds_read<WIDTH>(base + uint32_t(c) * 1024u);
+            base = (base + 19u * 128u) & uint32_t(kProbeBytes / 2 - 1);
+        }
+    } else if (MODE == kIndependent) {
         // base < 8 KiB, offsets <= 7 x 1022: every address < 16 KiB; even for 2-byte reads
         uint32_t base = mix(tid) & uint32_t(kProbeBytes / 2 - WIDTH);
         for (int64_t it = 0; it < iters; ++it) {
@@ -72,7 +88,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsi
             for (int c = 0; c < kReadsPerIter; ++c) acc += lds_read<WIDTH>(base + uint32_t(c) * kStride);
             base = (base + kAdvance) & uint32_t(kProbeBytes / 2 - WIDTH);
         }
-    } else {
+    } else {  // kDependent
         // row = value (< 128) x 128 bytes (1-byte entries) or x 64 entries (2-byte), column < 128 / 64
         uint32_t v[kReadsPerIter];
 #pragma unroll
@@ -92,23 +108,25 @@ __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsi
     if (acc == 0xffffffffu) sink[0] = acc;  // never true (values < 128): keeps the reads
 }
 
-const void *probe_fn(int width, int dep) {
-    if (width == 1) return dep ? reinterpret_cast<const void *>(&k_lds_probe<1, true>)
-                               : reinterpret_cast<const void *>(&k_lds_probe<1, false>);
-    return dep ? reinterpret_cast<const void *>(&k_lds_probe<2, true>)
-               : reinterpret_cast<const void *>(&k_lds_probe<2, false>);
+template <int WIDTH>
+const void *probe_fn_w(int mode) {
+    if (mode == kDependent) return reinterpret_cast<const void *>(&k_lds_probe<WIDTH, kDependent>);
+    if (mode == kLinear) return reinterpret_cast<const void *>(&k_lds_probe<WIDTH, kLinear>);
+    return reinterpret_cast<const void *>(&k_lds_probe<WIDTH, kIndependent>);
 }
+
+const void *probe_fn(int width, int mode) { return width == 1 ? probe_fn_w<1>(mode) : probe_fn_w<2>(mode); }
 
 }  // namespace
 
-extern "C" int64_t dfa_lds_probe(int32_t width, int32_t dependent, int32_t blocks, int64_t iters,
+extern "C" int64_t dfa_lds_probe(int32_t width, int32_t mode, int32_t blocks, int64_t iters,
                                  unsigned long long *sink, void *stream) {
-    if ((width != 1 && width != 2) || (dependent != 0 && dependent != 1) || blocks < 1 || blocks > (1 << 20) ||
+    if ((width != 1 && width != 2) || mode < 0 || mode > 2 || blocks < 1 || blocks > (1 << 20) ||
         iters < 1 || iters > (int64_t(1) << 24) || !sink || (reinterpret_cast<uintptr_t>(sink) & 7)) {
         dfa::set_error("dfa_lds_probe: bad arguments");
         return DFA_EINVAL;
     }
-    const void *fn = probe_fn(width, dependent);
+    const void *fn = probe_fn(width, mode);
     if (!dfa::allow_lds(fn, kProbeBytes)) return DFA_EHIP;
     int64_t it = iters;
     void *args[] = {&it, &sink};

@@ -837,14 +837,19 @@ constexpr int kRewalkGroups = 256;
 // it starts; from the start state at a, no match that starts before a can be
 // completed).  WRITE: the k-th of them goes to positions[off + k] (below cap).
 // a is a multiple of 4.  The bytes come 16 at a time as four words, the next
-// 16 requested before the current ones are walked.
-__device__ __forceinline__ void rewalk_fetch(const uint8_t *text, int64_t n, int64_t j0, int64_t lim,
-                                             uint32_t (&w)[4]) {
+// 16 requested before the current ones are walked, from the text in global
+// memory, or (STAGED) from the wave's bytes staged in LDS, byte j at
+// staged[j - base].
+template <bool STAGED>
+__device__ __forceinline__ void rewalk_fetch(const uint8_t *text, int64_t n, const uint8_t *staged, int64_t base,
+                                             int64_t j0, int64_t lim, uint32_t (&w)[4]) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t j = j0 + 4 * k;
         if (j >= lim) {
             w[k] = 0;
+        } else if (STAGED) {
+            w[k] = *reinterpret_cast<const uint32_t *>(staged + (j - base));  // staged up to lim, padded to 16
         } else if (j + 4 <= n) {
             w[k] = *reinterpret_cast<const uint32_t *>(text + j);
         } else {
@@ -855,16 +860,17 @@ __device__ __forceinline__ void rewalk_fetch(const uint8_t *text, int64_t n, int
     }
 }
 
-template <bool WRITE>
-__device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n, const unsigned char *tab, uint32_t m,
-                                                 int64_t a, int64_t b, int64_t off, int64_t *positions, int64_t cap,
-                                                 int64_t &s0, int64_t &s1) {
+template <bool WRITE, bool STAGED>
+__device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n, const uint8_t *staged, int64_t base,
+                                                 const unsigned char *tab, uint32_t m, int64_t a, int64_t b,
+                                                 int64_t off, int64_t *positions, int64_t cap, int64_t &s0,
+                                                 int64_t &s1) {
     const int64_t lim = b + int64_t(m) - 1 < n ? b + int64_t(m) - 1 : n;
     uint32_t q = 0, c = 0;
     uint32_t cur[4], nxt[4];
-    rewalk_fetch(text, n, a, lim, cur);
+    rewalk_fetch<STAGED>(text, n, staged, base, a, lim, cur);
     for (int64_t j0 = a; j0 < lim; j0 += 16) {
-        rewalk_fetch(text, n, j0 + 16, lim, nxt);
+        rewalk_fetch<STAGED>(text, n, staged, base, j0 + 16, lim, nxt);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             q = tab[q * uint32_t(kRow) + ((cur[k / 4] >> (8 * (k % 4))) & 0xffu)];
@@ -886,6 +892,18 @@ __device__ __forceinline__ uint32_t rewalk_share(const uint8_t *text, int64_t n,
     return c;
 }
 
+// LDS of k_rewalk: the table, the block scan's slots, and (staged) one listed
+// wave's bytes: its 64 spans plus the m - 1 after them, padded to 16
+__host__ __device__ inline int64_t rewalk_stage_offset(int m) { return table_lds_bytes(m) + 256; }
+__host__ __device__ inline int64_t rewalk_lds_bytes(int m, int64_t S, bool staged) {
+    return rewalk_stage_offset(m) + (staged ? (kWave * S + m - 1 + 15) / 16 * 16 + 16 : 0);
+}
+
+// STAGED: each listed wave's bytes are first copied to LDS with coalesced
+// 16-byte loads by the whole workgroup, so that the shares (a few dozen bytes
+// each, overlapping by m - 1) are walked from LDS instead of each thread
+// waiting on its own chain of global loads.
+template <bool STAGED>
 __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, int64_t n, const uint8_t *table,
                                                            int32_t m, int64_t S, const uint32_t *list,
                                                            const uint32_t *list_count, const int64_t *wave_off,
@@ -901,6 +919,7 @@ __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, 
             *reinterpret_cast<uint32_t *>(smem + (i >> 6) * kRow + 4 * (i & 63)) = tg[i];
     }
     unsigned long long *sh = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(m));
+    uint8_t *staged = smem + rewalk_stage_offset(m);
     __syncthreads();
     int64_t share = (kWave * S / kRewalkThreads + 15) / 16 * 16;  // S is a multiple of 16
     if (share < 16) share = 16;
@@ -908,14 +927,33 @@ __global__ __launch_bounds__(kRewalkThreads) void k_rewalk(const uint8_t *text, 
         const int64_t gw = list[i];
         const int64_t start = gw * kWave * S;
         const int64_t end = start + kWave * S < n ? start + kWave * S : n;
+        if (STAGED) {
+            // bytes [start, min(n, end + m - 1)): start is 16-byte aligned; past n zeros
+            const int64_t lim = end + m - 1 < n ? end + m - 1 : n;
+            __syncthreads();  // the previous wave's shares are walked
+            for (int64_t k = int64_t(t) * 16; start + k < lim; k += int64_t(kRewalkThreads) * 16) {
+                v4u v;
+                if (start + k + 16 <= n) {
+                    v = *reinterpret_cast<const v4u *>(text + start + k);
+                } else {
+                    uint32_t w4[4] = {0u, 0u, 0u, 0u};
+                    for (int e = 0; start + k + e < n; ++e) w4[e / 4] |= uint32_t(text[start + k + e]) << (8 * (e % 4));
+                    v = v4u{w4[0], w4[1], w4[2], w4[3]};
+                }
+                *reinterpret_cast<v4u *>(staged + k) = v;
+            }
+            __syncthreads();
+        }
         const int64_t a = start + t * share;
         const int64_t b = a + share < end ? a + share : end;
         int64_t s0 = 0, s1 = 0;  // the first two match starts, kept by the counting walk
-        const uint32_t c = a < b ? rewalk_share<false>(text, n, smem, uint32_t(m), a, b, 0, nullptr, 0, s0, s1) : 0u;
+        const uint32_t c = a < b ? rewalk_share<false, STAGED>(text, n, staged, start, smem, uint32_t(m), a, b, 0,
+                                                               nullptr, 0, s0, s1)
+                                 : 0u;
         unsigned long long total;
         const int64_t off = wave_off[gw] + int64_t(block_exclusive_scan(c, sh, &total));
         if (c > 2) {
-            rewalk_share<true>(text, n, smem, uint32_t(m), a, b, off, positions, cap, s0, s1);
+            rewalk_share<true, STAGED>(text, n, staged, start, smem, uint32_t(m), a, b, off, positions, cap, s0, s1);
         } else {
             if (c > 0 && off < cap) positions[off] = s0;
             if (c > 1 && off + 1 < cap) positions[off + 1] = s1;
@@ -1034,7 +1072,11 @@ bool check_tune(const dfa_tune *t) {
         dfa::set_error("tune: negative field");
         return false;
     }
-    for (int i = 0; i < 3; ++i)
+    if (t->step_bytes < 0 || t->step_bytes > 2) {
+        dfa::set_error("tune.step_bytes=%d must be 1 or 2 (or 0)", t->step_bytes);
+        return false;
+    }
+    for (int i = 0; i < 2; ++i)
         if (t->reserved[i]) {
             dfa::set_error("tune.reserved must be zero");
             return false;
@@ -1295,12 +1337,21 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
                            (const unsigned long long *)sup, dfa::ceil_div(nw, kWave), pl.wpg, per_block, woff, flag,
                            list_count);
         if (!hip_ok(hipGetLastError(), "placement launch")) return DFA_EHIP;
-        const int rw_lds = table_lds_bytes(m) + kRewalkThreads / kWave * 8;
-        if (!dfa::allow_lds(reinterpret_cast<const void *>(&k_rewalk), table_lds_bytes(DFA_MAX_M) + 256))
-            return DFA_EHIP;
-        hipLaunchKernelGGL(k_rewalk, dim3(unsigned(std::min<int64_t>(kRewalkGroups, dfa::ceil_div(nw, kWave)))),
-                           dim3(kRewalkThreads), rw_lds, st, text, n, table, m, pl.S, (const uint32_t *)flag,
-                           (const uint32_t *)list_count, (const int64_t *)woff, positions, cap);
+        // the listed waves' bytes staged in LDS when they fit next to the table
+        const bool staged = rewalk_lds_bytes(m, pl.S, true) <= int64_t(kLdsPerCu);
+        const void *rw = staged ? reinterpret_cast<const void *>(&k_rewalk<true>)
+                                : reinterpret_cast<const void *>(&k_rewalk<false>);
+        if (!dfa::allow_lds(rw, int(kLdsPerCu))) return DFA_EHIP;
+        const dim3 rw_grid(unsigned(std::min<int64_t>(kRewalkGroups, dfa::ceil_div(nw, kWave))));
+        const size_t rw_lds = size_t(rewalk_lds_bytes(m, pl.S, staged));
+        if (staged)
+            hipLaunchKernelGGL(k_rewalk<true>, rw_grid, dim3(kRewalkThreads), rw_lds, st, text, n, table, m, pl.S,
+                               (const uint32_t *)flag, (const uint32_t *)list_count, (const int64_t *)woff, positions,
+                               cap);
+        else
+            hipLaunchKernelGGL(k_rewalk<false>, rw_grid, dim3(kRewalkThreads), rw_lds, st, text, n, table, m, pl.S,
+                               (const uint32_t *)flag, (const uint32_t *)list_count, (const int64_t *)woff, positions,
+                               cap);
         if (!hip_ok(hipGetLastError(), "k_rewalk launch")) return DFA_EHIP;
         dfa::clear_error();
         return DFA_OK;

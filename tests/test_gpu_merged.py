@@ -156,3 +156,45 @@ def test_many_patterns_scale():
         want = list(ex.map(lambda p: oracle.count(w.text, p), w.patterns))
     for j, c in enumerate(want):
         assert got[j] == c, j
+
+
+def _plan_pair_items(b):
+    return b.plan.pair_items  # items walked two bytes per step
+
+
+@pytest.mark.parametrize("step", [1, 2, 0])
+def test_pair_and_one_step_automata(step):
+    """Two bytes per step (pair automata) and one byte per step give the oracle's counts:
+    segments of uneven length, all pattern lengths, a dense periodic text (every pair has a
+    reporting state after its first byte) and degenerate queries on both strands."""
+    t = api.tune(step_bytes=step, automaton_bytes=64 * 1024) if step else None
+    w = synth.uneven_segments(nseg=120, median=30_000, sigma=1.5, lo=1, hi=1_500_000, seed=17)
+    say("step", step, "segments", w.seg_off.size - 1, "pairs", w.pair_seg.size)
+    check(w.text, w.seg_off, w.patterns, w.pair_seg, w.pair_pat, t)
+    b = api.MergedBatch(w.seg_off, w.patterns, w.pair_seg, w.pair_pat, t)
+    npi = _plan_pair_items(b)
+    assert (npi == 0) if step == 1 else (npi > 0), (step, npi, b.plan.nitems)
+    text = synth.genome_like(2_000_003, 47, 0.02, 3000)
+    rng = np.random.default_rng(12)
+    pats = _mixed_patterns(text, rng, LENGTHS * 3)
+    check(text, [0, text.size], pats, [0] * len(pats), list(range(len(pats))), t)
+    dense = np.full(700_001, ord("A"), np.uint8)
+    dense[::97] = ord("C")
+    dp = [b"A", b"AA", b"AAA", b"A" * 8, b"A" * 33, b"CA", b"AC", b"ACA", b"CAAAAAAAAAAAAAAAAAAAAAAAAAAAAAAAAAAC"]
+    seg = [0, 1, 2, 3, 100_000, 100_001, 400_000, dense.size]
+    ps_ = [s for s in range(len(seg) - 1) for _ in dp]
+    pp_ = [j for _ in range(len(seg) - 1) for j in range(len(dp))]
+    check(dense, seg, dp, ps_, pp_, t)
+    # degenerate queries (one automaton of k-mers and their reverse complements)
+    qrng = np.random.default_rng(13)
+    codes = []
+    for i in range(6):
+        c = list(synth.random_pattern(8, qrng).decode())
+        c[i % 8] = "BDHV"[i % 4]
+        codes.append("".join(c).encode())
+    d = api.to_device(text)
+    got = api.count_degenerate(d, [0, 1_000_000, text.size], [(i % 2, c, True) for i, c in enumerate(codes)], t)
+    seg_d = [(0, 1_000_000), (1_000_000, text.size)]
+    for i, c in enumerate(codes):
+        lo, hi = seg_d[i % 2]
+        assert got[i] == oracle.degenerate_count(text[lo:hi], c, True), c

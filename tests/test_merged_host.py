@@ -185,3 +185,28 @@ def test_merged_decomposition_model_matches_oracle(seed):
     for S, wpt in ((128, 2), (256, 3), (1024, 1)):
         got = _model_counts(text, seg_off, pats, pair_seg, pair_pat, S, wpt)
         assert np.array_equal(got, want), (S, wpt)
+
+
+def test_merged_prepare_pair_automata():
+    """Pair automata (two bytes per step): small automata over few byte classes take
+    them by default, step_bytes=1 turns them off, step_bytes=2 packs patterns so that
+    every automaton fits as one, and their items are planned first."""
+    rng = np.random.default_rng(6)
+    pats = _random_set(rng, 6, 6, 12)
+    n = len(pats)
+    _, dflt = _prepare([0, 1 << 20], pats, [0] * n, list(range(n)))
+    assert dflt.pair_items == dflt.nitems > 0          # every item's automaton is a pair automaton
+    _, one = _prepare([0, 1 << 20], pats, [0] * n, list(range(n)), api.tune(step_bytes=1))
+    assert one.pair_items == 0 and one.nitems == dflt.nitems
+    many = _random_set(rng, 300, 20, 40)
+    m = len(many)
+    _, single = _prepare([0, 1 << 20], many, [0] * m, list(range(m)))
+    _, paired = _prepare([0, 1 << 20], many, [0] * m, list(range(m)), api.tune(step_bytes=2))
+    assert single.pair_items == 0                       # large automata stay one-step
+    assert paired.nautomata > single.nautomata and paired.pair_items == paired.nitems
+    # more byte classes than a pair automaton takes: one-step only
+    wide = [bytes(range(i, i + 12)) for i in range(0, 240, 12)]
+    _, w = _prepare([0, 1 << 20], wide, [0] * len(wide), list(range(len(wide))), api.tune(step_bytes=2))
+    assert w.pair_items == 0
+    rc, _ = _prepare([0, 1000], pats, [0], [0], api.tune(step_bytes=3))
+    assert rc == api.DFA_EINVAL
