@@ -107,6 +107,17 @@ constexpr int64_t kMaxPositionsSpan = 65536;
 
 __host__ __device__ inline int table_lds_bytes(int m) { return table_lds_rows_bytes(m + 1); }
 
+// The per-walk counting pass and the positions pass with one walk per lane
+// (used for m < kPerWaveMinM) keep a MARKED table in LDS: entry 2 q + f, f = 1
+// iff q = m is the final state, every row stored twice (rows 2 q and 2 q + 1
+// are state q's), so that the walk register holds the entry itself and one
+// funnel shift per byte records whether it is final.  The final test is
+// entry == 2 m + 1.
+__host__ __device__ constexpr bool marked_table(int K, int mode) { return K == 1 && (mode == 1 || mode == 2); }
+__host__ __device__ inline int scan_table_bytes(int m, int K, int mode) {
+    return marked_table(K, mode) ? table_lds_rows_bytes(2 * (m + 1)) : table_lds_bytes(m);
+}
+
 struct WalkLane {
     int64_t wstart;  // first byte of the walk
     uint32_t len;    // bytes the walk reads (span + m - 1, clipped at the text end)
@@ -144,16 +155,26 @@ __device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m
     }
 }
 
+// The same from a marked walk's mask (walk16_marks: byte i of the unit in bit i).
+__device__ __forceinline__ void record_marks(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, const ScanParams &p) {
+    while (hm) {
+        const int b = __builtin_ctz(hm);
+        if (w.cnt < uint32_t(kBuffered)) put_record(p, 0, w.cnt, uint16_t(jb + uint32_t(b) - (m - 1)));
+        ++w.cnt;
+        hm &= hm - 1u;
+    }
+}
+
 // Walk 16 bytes: byte b of word w is byte jb + 4w + b of the walk.  GUARD:
 // only bytes below the walk's length count.  kCount: ballot + scalar count.
 // kCountPerWalk: per-walk count and the first kBuffered match starts (the
 // total is summed from the per-walk counts at the end).  kPositions: write
 // the start offset of every match.
 template <int K, int MODE, bool GUARD>
-__device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
+__device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t mhit, uint32_t jb,
                                           uint32_t &acc, WalkLane (&wl)[K], const ScanParams &p) {
     if constexpr (MODE == kCount && !GUARD && K == 1) {
-        walk16_count(q[0], t[0], acc, m);
+        walk16_count(q[0], t[0], acc, mhit);
         return;
     }
 
@@ -165,20 +186,21 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
         // unit with matches it walks the next one with hit masks directly.
         // `acc` carries the choice (nonzero: hit masks); the per-walk counts
         // live in wl and `acc` is rewritten with their sum at the end.
+        // (one walk per lane: the table is marked, see marked_table)
         uint32_t hm;
         if (__builtin_amdgcn_readfirstlane(acc)) {
-            walk16_hits(q[0], t[0], hm, m);
+            walk16_marks(q[0], t[0], hm);
             const bool any = __ballot(hm != 0) != 0;
-            if (any) record_hits(hm, jb, m, wl[0], p);
+            if (any) record_marks(hm, jb, m, wl[0], p);
             acc = any ? 1u : 0u;
         } else {
             const uint32_t q0 = q[0];
             uint32_t a = 0;
-            walk16_count(q[0], t[0], a, m);
+            walk16_count(q[0], t[0], a, mhit);
             if (__builtin_amdgcn_readfirstlane(a)) {
                 q[0] = q0;
-                walk16_hits(q[0], t[0], hm, m);
-                record_hits(hm, jb, m, wl[0], p);
+                walk16_marks(q[0], t[0], hm);
+                record_marks(hm, jb, m, wl[0], p);
                 acc = 1u;
             }
         }
@@ -193,7 +215,7 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
                 const uint32_t c = (t[s][w] >> (8 * b)) & 0xffu;
                 const uint32_t j = jb + uint32_t(4 * w + b);
                 q[s] = table_step(q[s], c);
-                bool hit = q[s] == m;
+                bool hit = q[s] == mhit;
                 if (GUARD) hit = hit && (j < wl[s].len);
                 if (MODE == kCount) {
                     add_hits(acc, hit);
@@ -218,19 +240,21 @@ __device__ __forceinline__ void walk_unit(const v4u (&t)[K], uint32_t (&q)[K], u
 // overlap (the count-only mode adds the lane's hits to `extra`, summed over
 // the wave at the end); otherwise the byte loop with its length check.
 template <int K, int MODE>
-__device__ __forceinline__ void walk_overlap_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t jb,
-                                                  uint32_t nvalid, uint32_t &acc, uint32_t &extra,
+__device__ __forceinline__ void walk_overlap_unit(const v4u (&t)[K], uint32_t (&q)[K], uint32_t m, uint32_t mhit,
+                                                  uint32_t jb, uint32_t nvalid, uint32_t &acc, uint32_t &extra,
                                                   WalkLane (&wl)[K], const ScanParams &p) {
-    if constexpr (K == 1 && MODE != kPositions) {
+    if constexpr (K == 1 && MODE == kCount) {
         uint32_t hm;
         walk16_hits(q[0], t[0], hm, m);
         hm &= 0xffffu & ~((1u << (16u - nvalid)) - 1u);  // byte i of the unit is bit 15 - i
-        if (MODE == kCount)
-            extra += uint32_t(__popc(hm));
-        else if (__ballot(hm != 0))
-            record_hits(hm, jb, m, wl[0], p);
+        extra += uint32_t(__popc(hm));
+    } else if constexpr (K == 1 && MODE == kCountPerWalk) {
+        uint32_t hm;
+        walk16_marks(q[0], t[0], hm);
+        hm &= (1u << nvalid) - 1u;  // byte i of the unit is bit i
+        if (__ballot(hm != 0)) record_marks(hm, jb, m, wl[0], p);
     } else {
-        walk_unit<K, MODE, true>(t, q, m, jb, acc, wl, p);
+        walk_unit<K, MODE, true>(t, q, m, mhit, jb, acc, wl, p);
     }
 }
 
@@ -239,7 +263,7 @@ __device__ __forceinline__ void walk_overlap_unit(const v4u (&t)[K], uint32_t (&
 // belong to every walk when GUARD is false; with GUARD, each walk's own length
 // decides.
 template <int K, int LINE, int MODE, bool GUARD>
-__device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q)[K], uint32_t m,
+__device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q)[K], uint32_t m, uint32_t mhit,
                                            uint32_t rb, int nbytes, uint32_t &acc, WalkLane (&wl)[K],
                                            const ScanParams &p) {
     using G = Geo<LINE>;
@@ -254,9 +278,9 @@ __device__ __forceinline__ void walk_round(const v4u *xb, int lane, uint32_t (&q
         }
         const uint32_t jb = rb + uint32_t(16 * u);
         if (GUARD || 16 * (u + 1) > nbytes)
-            walk_unit<K, MODE, true>(cur, q, m, jb, acc, wl, p);
+            walk_unit<K, MODE, true>(cur, q, m, mhit, jb, acc, wl, p);
         else
-            walk_unit<K, MODE, false>(cur, q, m, jb, acc, wl, p);
+            walk_unit<K, MODE, false>(cur, q, m, mhit, jb, acc, wl, p);
 #pragma unroll
         for (int s = 0; s < K; ++s) cur[s] = nxt[s];
     }
@@ -283,7 +307,8 @@ constexpr int scan_waves_per_eu() {
 // kPositions.
 template <int K, int LINE, int WM, int H>
 __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane, int64_t g0, uint32_t m,
-                                          uint32_t lane_off, uint32_t (&q)[K], uint32_t &acc, WalkLane (&wl)[K]) {
+                                          uint32_t mhit, uint32_t lane_off, uint32_t (&q)[K], uint32_t &acc,
+                                          WalkLane (&wl)[K]) {
     using G = Geo<LINE>;
     // whole wave in bounds: every load of every round lies inside the text
     const int64_t glast = g0 + kWave * K - 1;
@@ -331,16 +356,16 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
             fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, 0, rlast);
             stage_pair<K, 0>(pp, xb, lane);
             grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, G::U);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, LINE, acc, wl, p);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, 0u, LINE, acc, wl, p);
             stage_pair<K, 1>(pp, xb, lane);
             fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, 2, rlast);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), LINE, acc, wl, p);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t(LINE), LINE, acc, wl, p);
             for (int r = 2; r < R; r += 2) {
                 stage_pair<K, 0>(pp, xb, lane);
-                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t(r * LINE), LINE, acc, wl, p);
                 stage_pair<K, 1>(pp, xb, lane);
                 fetch_pair<K>(pp, p.text, wb, p.S, pair_off, lane, r + 2, rlast);
-                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE), LINE, acc, wl, p);
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t((r + 1) * LINE), LINE, acc, wl, p);
             }
         } else {
             v4u pa[K][G::U], pb[K][G::U];
@@ -350,26 +375,26 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
             stage_round<K, LINE>(pa, xb, lane);
             grab_halo<K, LINE, H>(halo, xb, lane, p.text, wb, p.S, hu, rlast == 0 ? int(ulast) : G::U);
             if (LINE == 128) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
-            walk_round<K, LINE, WM, false>(xb, lane, q, m, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
+            walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, 0u, rlast == 0 ? lastlen : LINE, acc, wl, p);
             if (rlast >= 1) {
                 stage_round<K, LINE>(pb, xb, lane);
                 if (LINE == 64) fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, 2, rlast);
                 fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, 3, rlast);
-                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t(LINE), rlast == 1 ? lastlen : LINE, acc, wl,
                                                  p);
             }
             for (int r = 2; r < R; r += 2) {
                 stage_round<K, LINE>(pa, xb, lane);
                 if (LINE == 128)
                     fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
-                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t(r * LINE), r == rlast ? lastlen : LINE,
                                                  acc, wl, p);
                 if (r + 1 > rlast) break;
                 stage_round<K, LINE>(pb, xb, lane);
                 if (LINE == 64)
                     fetch_round_or_none<K, LINE>(pa, p.text, wb, p.S, lane_off, off_last, off_none, r + 2, rlast);
                 fetch_round_or_none<K, LINE>(pb, p.text, wb, p.S, lane_off, off_last, off_none, r + 3, rlast);
-                walk_round<K, LINE, WM, false>(xb, lane, q, m, uint32_t((r + 1) * LINE),
+                walk_round<K, LINE, WM, false>(xb, lane, q, m, mhit, uint32_t((r + 1) * LINE),
                                                  r + 1 == rlast ? lastlen : LINE, acc, wl, p);
             }
         }
@@ -383,7 +408,7 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
 #pragma unroll
                 for (int s = 0; s < K; ++s) t[s] = halo[s][u];
                 const uint32_t nv = m - 1 - 16u * u;
-                walk_overlap_unit<K, WM>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
+                walk_overlap_unit<K, WM>(t, q, m, mhit, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
             }
         }
         for (int u = H; u < hu; ++u) {
@@ -392,7 +417,7 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
             for (int s = 0; s < K; ++s)
                 t[s] = *reinterpret_cast<const v4u *>(p.text + (g0 + s * kWave + lane + 1) * p.S + 16 * u);
             const uint32_t nv = m - 1 - 16u * u;
-            walk_overlap_unit<K, WM>(t, q, m, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
+            walk_overlap_unit<K, WM>(t, q, m, mhit, hb + 16u * u, nv < 16u ? nv : 16u, acc, extra, wl, p);
         }
         if (WM == kCount && K == 1) {
             // the overlap's hits, summed over the wave
@@ -407,7 +432,7 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
         for (int r = 0; r < p.rounds; ++r) {
             stage_round<K, LINE>(pf, xb, lane);
             if (r + 1 < p.rounds) fetch_round<K, LINE, true>(pf, p.text, p.n, g0 * p.S, p.S, lane_off, r + 1);
-            walk_round<K, LINE, WM, true>(xb, lane, q, m, uint32_t(r * LINE), LINE, acc, wl, p);
+            walk_round<K, LINE, WM, true>(xb, lane, q, m, mhit, uint32_t(r * LINE), LINE, acc, wl, p);
         }
     }
 
@@ -428,18 +453,34 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const int nwaves = blockDim.x / kWave;
     // table first (LDS address 0), then one transpose buffer per wave
-    v4u *xb = reinterpret_cast<v4u *>(smem + table_lds_bytes(p.m) + wave * (K * kWave * LINE));
+    constexpr bool kMarked = marked_table(K, MODE);
+    const int tbytes = scan_table_bytes(p.m, K, MODE);
+    v4u *xb = reinterpret_cast<v4u *>(smem + tbytes + wave * (K * kWave * LINE));
 
     // only walks whose matches did not all fit the counting pass's buffer are
     // walked again: a workgroup without any leaves before loading the table
     if (MODE == kPositions && p.wg_flag[blockIdx.x] == 0) return;
 
-    // table -> LDS, rows padded to kRow bytes
+    // table -> LDS, rows padded to kRow bytes (marked: entries 2 q + [q == m],
+    // each row twice)
     {
         const uint32_t *tg = reinterpret_cast<const uint32_t *>(p.table);
         const int words = (p.m + 1) * (DFA_ALPHABET / 4);
-        for (int i = threadIdx.x; i < words; i += blockDim.x)
-            *reinterpret_cast<uint32_t *>(smem + (i >> 6) * kRow + 4 * (i & 63)) = tg[i];
+        for (int i = threadIdx.x; i < words; i += blockDim.x) {
+            const uint32_t w = tg[i];
+            if (kMarked) {
+                uint32_t e = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t b = (w >> (8 * k)) & 0xffu;
+                    e |= (2u * b + (b == uint32_t(p.m) ? 1u : 0u)) << (8 * k);
+                }
+                *reinterpret_cast<uint32_t *>(smem + (2 * (i >> 6)) * kRow + 4 * (i & 63)) = e;
+                *reinterpret_cast<uint32_t *>(smem + (2 * (i >> 6) + 1) * kRow + 4 * (i & 63)) = e;
+            } else {
+                *reinterpret_cast<uint32_t *>(smem + (i >> 6) * kRow + 4 * (i & 63)) = w;
+            }
+        }
     }
     __syncthreads();
 
@@ -448,10 +489,11 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
         p.walk_buf += g0 * kStaged;
         p.walk_buf1 += g0 * kStaged;
         p.rec_lds = stages_records(K, MODE, H) && p.stage
-                        ? uint32_t(table_lds_bytes(p.m) + nwaves * (K * kWave * LINE) + wave * kRecBytes)
+                        ? uint32_t(tbytes + nwaves * (K * kWave * LINE) + wave * kRecBytes)
                         : 0u;
     }
     const uint32_t m = uint32_t(p.m);
+    const uint32_t mhit = kMarked ? 2u * m + 1u : m;  // the final state's table entry
     const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(p.S) + 16u * uint32_t(lane % G::U);
 
     // per-lane walk bookkeeping
@@ -485,7 +527,8 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     if (MODE == kPositions && __ballot(any_work) == 0) return;  // nothing left to write in this wave
 
     uint32_t acc = 0;
-    walk_wave<K, LINE, MODE == kCountPerWave ? int(kCount) : MODE, H>(p, xb, lane, g0, m, lane_off, q, acc, wl);
+    walk_wave<K, LINE, MODE == kCountPerWave ? int(kCount) : MODE, H>(p, xb, lane, g0, m, mhit, lane_off, q, acc,
+                                                                       wl);
 
     if (MODE == kPositions) return;
 
@@ -524,7 +567,7 @@ void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.wal
     }
     // workgroup sum in LDS (reusing the first transpose buffer): one atomic,
     // or (per-walk counting) the workgroup's total for the placement scan
-    unsigned long long *red = reinterpret_cast<unsigned long long *>(smem + table_lds_bytes(p.m));
+    unsigned long long *red = reinterpret_cast<unsigned long long *>(smem + tbytes);
     __syncthreads();
     if (lane == 0) red[wave] = acc;
     __syncthreads();
@@ -1016,7 +1059,9 @@ bool per_wave_plan(int K, int m) { return K == 1 && m >= kPerWaveMinM; }
 
 size_t scan_lds_bytes(int wpg, int K, int line, int m, int mode) {
     const bool rec = plan_stages(K, m, mode);
-    return size_t(wpg) * (K * kWave * line + (rec ? kRecBytes : 0)) + size_t(table_lds_bytes(m));
+    // the positions pass runs with the counting pass's plan: size its table as marked too
+    const int tmode = mode == kPositions ? int(kCountPerWalk) : mode;
+    return size_t(wpg) * (K * kWave * line + (rec ? kRecBytes : 0)) + size_t(scan_table_bytes(m, K, tmode));
 }
 
 // Default span of one walk, in whole 128-byte lines: 512 bytes up to m = 16,

@@ -301,6 +301,100 @@ __device__ __forceinline__ void walk16_hits(uint32_t &q, const v4u &t, uint32_t 
         : [w0] "v"(t.x), [w1] "v"(t.y), [w2] "v"(t.z), [w3] "v"(t.w), [m] "s"(m), [row] "s"(uint32_t(kRow)));
 }
 
+// The same sixteen steps over a MARKED table: entry 2 q + f for the state q
+// reached, f = 1 iff q is final, with row e at e x kRow holding state e / 2's
+// transitions (each row stored twice), so the walk's register holds entries.
+// One funnel shift per byte moves the entry's low bit into `hm`: byte i of the
+// unit ends in bit i (the first byte in bit 0).  No compare is needed.
+__device__ __forceinline__ void walk16_marks(uint32_t &q, const v4u &t, uint32_t &hm) {
+    uint32_t qb, a, c;
+    hm = 0;  // shifted out: only the 16 bits the steps insert are kept
+    asm(
+        "v_bfe_u32 %[c], %[w0], 0, 8\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 8, 8\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 16, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w0], 24, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 0, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 8, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 16, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w1], 24, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 0, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 8, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 16, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w2], 24, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 0, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 8, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 16, 8\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[q], %[row], %[c]\n\t"
+        "ds_read_u8 %[qb], %[a]\n\t"
+        "v_bfe_u32 %[c], %[w3], 24, 8\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_mad_u32_u24 %[a], %[qb], %[row], %[c]\n\t"
+        "ds_read_u8 %[q], %[a]\n\t"
+        "v_alignbit_b32 %[hm], %[qb], %[hm], 1\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_alignbit_b32 %[hm], %[q], %[hm], 1\n\t"
+        : [q] "+v"(q), [qb] "=&v"(qb), [a] "=&v"(a), [c] "=&v"(c), [hm] "+v"(hm)
+        : [w0] "v"(t.x), [w1] "v"(t.y), [w2] "v"(t.z), [w3] "v"(t.w), [row] "s"(uint32_t(kRow)));
+    hm >>= 16;
+}
+
 // 16 bytes at text[a..a+15]; bytes at or past n read as 0 (a byte outside
 // every pattern: it sends the automaton to q0 and never completes a match).
 __device__ __forceinline__ v4u load_unit_guarded(const uint8_t *text, int64_t n, int64_t a) {
