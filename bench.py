@@ -153,29 +153,40 @@ def oracle_mod():
 
 
 def cpu_automaton_baseline(text, pats, counts, pos_bufs):
-    """The oracle's plain automaton scan (its C function, one thread) over the whole text for
-    every pattern: count and positions in one pass into a buffer sized from the GPU's count;
-    returns the baseline and whether every count and position equals the GPU's."""
+    """The oracle's plain automaton scan (its C function) over the whole text for every
+    pattern, one thread per pattern, the patterns side by side: count and positions in one
+    pass into a buffer sized from the GPU's count.  Returns the baseline and whether every
+    count and position equals the GPU's."""
     import ctypes
+    from concurrent.futures import ThreadPoolExecutor
     o = oracle_mod()
-    lib = o._load().lib
+    lib = o.OracleLib(o.build(force=False)).lib
     u8p, i64p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int64)
     n = text.size
-    secs, ok = 0.0, True
-    for i, p in enumerate(pats):
-        tab = np.ascontiguousarray(o.transition_table(p))
-        out = np.empty(max(1, counts[i]), np.int64)
+    tabs = [np.ascontiguousarray(o.transition_table(p)) for p in pats]
+    outs = [np.empty(max(1, c), np.int64) for c in counts]
+
+    def scan(i):
         t0 = time.perf_counter()
-        c = lib.oracle_automaton_scan(tab.ctypes.data_as(u8p), len(p), text.ctypes.data_as(u8p), n,
-                                      out.ctypes.data_as(i64p), out.size)
-        secs += time.perf_counter() - t0
+        c = lib.oracle_automaton_scan(tabs[i].ctypes.data_as(u8p), len(pats[i]), text.ctypes.data_as(u8p), n,
+                                      outs[i].ctypes.data_as(i64p), outs[i].size)
+        return c, time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=len(pats)) as ex:
+        res = list(ex.map(scan, range(len(pats))))
+    wall = time.perf_counter() - t0
+    ok = True
+    for i, (c, _) in enumerate(res):
         g = pos_bufs[i][:counts[i]].cpu().numpy()
-        ok &= bool(c == counts[i] and np.array_equal(out[:c], g))
-        log(f"  cpu automaton scan m={len(p)}: {c} matches")
-    return ({"value": round(n * len(pats) / secs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-             "sample": f"the whole {n}-byte text, the same {len(pats)} patterns one after another: "
-                       f"the oracle's automaton scan (build of the table excluded), count + positions "
-                       f"in one pass, {secs:.1f} s on {cpu_model()}"}, ok)
+        ok &= bool(c == counts[i] and np.array_equal(outs[i][:c], g))
+    per_core = [n / s / 1e9 for _, s in res]
+    log(f"  cpu automaton scans: {wall:.1f} s, per core {[round(x, 3) for x in per_core]} GB/s")
+    return ({"value": round(n * len(pats) / wall / 1e9, 4), "unit": "GB/s", "cores": len(pats), "kind": "oracle",
+             "per_core_GBps": round(float(np.mean(per_core)), 4),
+             "sample": f"the whole {n}-byte text for each of the same {len(pats)} patterns, one thread per "
+                       f"pattern side by side: the oracle's automaton scan (table build excluded), count + "
+                       f"positions in one pass, {wall:.1f} s on {cpu_model()}"}, ok)
 
 
 def cpu_pairs_baseline(text, seg_off, patterns, pair_seg, pair_pat, budget):
@@ -292,6 +303,7 @@ def bench_degenerate(torch, api, d, n):
             "ms": round(ms, 3), "text_GBps": round(n / ms / 1e6, 1),
             "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
             "query_bytes_per_s": round(n * len(queries) / (ms * 1e-3), 1),
+            "pair_items": int(b.batch.plan.pair_items),
             "counts": [int(x) for x in b.counts.cpu().numpy()[:len(queries)]],
             "cpu_baseline": {"value": round(sn * len(queries) / cpu_s, 1), "unit": "query-bytes/s", "cores": cores,
                              "kind": "oracle",
@@ -299,12 +311,14 @@ def bench_degenerate(torch, api, d, n):
                                        f"threads, {cpu_s:.1f} s on {cpu_model()}"}}
 
 
-def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0):
+def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0, line_bytes=0, automaton_bytes=0):
     """The merged scans alone, for kernel traces and shader counters: the 1 GB x 1024-pattern
     plan, the 18 degenerate queries over the same text and the 2000-segment plan, each run
     `reps` times after one warm-up run, with the library's default plan (step_bytes: 1 or 2
-    forces one- or two-byte automaton steps)."""
-    t = api.tune(step_bytes=step_bytes) if step_bytes else None
+    forces one- or two-byte automaton steps; line_bytes: bytes per round; automaton_bytes: the LDS
+    budget of one merged automaton; 0: the library's choice)."""
+    t = (api.tune(step_bytes=step_bytes, line_bytes=line_bytes, automaton_bytes=automaton_bytes)
+         if step_bytes or line_bytes or automaton_bytes else None)
     from paper_1506_08612_amd import graph
     out = {}
     w = synth.many_patterns()
@@ -331,7 +345,8 @@ def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0):
         plan = b.batch.plan if hasattr(b, "batch") else b.plan
         out[name] = {"ms": round(ms, 4), "text_GBps": round(int(text.numel()) / ms / 1e6, 1),
                      "automata": int(plan.nautomata), "states": int(plan.nstates), "items": int(plan.nitems),
-                     "pair_items": int(plan.pair_items), "groups": [int(x) for x in plan.group_items]}
+                     "pair_items": int(plan.pair_items), "groups": [int(x) for x in plan.group_items],
+                     "line_bytes": int(plan.reserved[1]), "waves": int(plan.waves_per_group)}
         log(name, out[name])
     return out
 
@@ -478,8 +493,10 @@ def bench_segmented(torch, api, synth):
     cpu = cpu_pairs_baseline(w.text, w.seg_off, w.patterns, w.pair_seg, w.pair_pat, 600_000_000)
     return {"workload": f"{seg_len.size} segments, {int(w.seg_off[-1])} B, {w.pair_seg.size} (segment, pattern) pairs",
             "ms": round(ms, 3), "text_GBps": round(int(w.seg_off[-1]) / ms / 1e6, 1),
+            "hbm_frac": round(int(w.seg_off[-1]) / ms / 1e6 / HBM_PEAK_GBS, 4),
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems),
-            "method": "merged automata per segment, HIP graph replay",
+            "pair_items": int(b.plan.pair_items),
+            "method": "merged automata per segment (pair automata where they keep occupancy), HIP graph replay",
             "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal,
             "cpu_baseline": cpu}
 
@@ -531,6 +548,10 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--merged-step", type=int, default=0, choices=(0, 1, 2),
                     help="--only merged: bytes per automaton step (0: the library's choice)")
+    ap.add_argument("--merged-line", type=int, default=0, choices=(0, 32, 64),
+                    help="--only merged: bytes per round (0: the library's choice)")
+    ap.add_argument("--merged-automaton-bytes", type=int, default=0,
+                    help="--only merged: LDS budget of one merged automaton (0: the library's choice)")
     ap.add_argument("--no-study", action="store_true",
                     help="skip the size sweep and workgroup load-balance study of the scan")
     ap.add_argument("--only", choices=("batched", "segmented", "serving", "fasta", "lds", "merged"),
@@ -557,7 +578,9 @@ def main(argv=None) -> int:
                 "fasta": fasta_leg,
                 "serving": lambda: bench_serving(torch, a.serve_queries),
                 "lds": lambda: bench_lds(torch, api),
-                "merged": lambda: bench_merged_kernels(torch, api, synth, step_bytes=a.merged_step)}
+                "merged": lambda: bench_merged_kernels(torch, api, synth, step_bytes=a.merged_step,
+                                                        line_bytes=a.merged_line,
+                                                        automaton_bytes=a.merged_automaton_bytes)}
         print(json.dumps({a.only: legs[a.only]()}), flush=True)
         return 0
     stream = torch.cuda.current_stream()

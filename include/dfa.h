@@ -58,7 +58,8 @@ typedef struct dfa_tune {
     int32_t automaton_bytes; /* merged scans: LDS bytes one merged automaton may take
                               * (its table, byte-class map and final-state counters);
                               * decides how many patterns share one automaton */
-    int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 */
+    int32_t line_bytes;      /* bytes of every walk fetched per round: 64 or 128 (merged
+                              * scans: 32 or 64) */
     int32_t step_bytes;      /* merged scans: text bytes per automaton step, 1 or 2 (a pair
                               * table, where it fits automaton_bytes); other scans ignore it */
     int32_t reserved[2];     /* must be zero */
@@ -260,7 +261,7 @@ int64_t dfa_ac_build(const uint8_t *patterns, const int64_t *pat_off, const int3
                      int32_t npat, uint16_t *table, int64_t max_states, int32_t *first_final,
                      int32_t *out_off, int32_t *out_pat, int64_t out_cap, int64_t *n_out);
 
-#define DFA_MERGED_GROUPS 4
+#define DFA_MERGED_GROUPS 8
 typedef struct dfa_merged_plan {
     int64_t nitems;          /* work items: (tile of a segment, merged automaton) */
     int64_t nautomata;       /* merged automata built */

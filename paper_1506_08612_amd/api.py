@@ -25,7 +25,7 @@ DFA_EINVAL = -1
 DFA_EHIP = -2
 DFA_ENOSPACE = -3
 MAX_M = 255
-MERGED_GROUPS = 4  # DFA_MERGED_GROUPS
+MERGED_GROUPS = 8  # DFA_MERGED_GROUPS
 NOALLOC_SCRATCH_BYTES = 64 << 20  # DFA_NOALLOC_SCRATCH_BYTES
 ALPHABET = 256
 

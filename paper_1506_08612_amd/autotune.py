@@ -39,11 +39,11 @@ BATCH_CANDIDATES: List[Dict[str, int]] = [
 ]
 
 MERGED_CANDIDATES: List[Dict[str, int]] = [
-    dict(),  # library default (48 KiB automata, 8 waves)
-    dict(automaton_bytes=24 * 1024, waves_per_group=8),
-    dict(automaton_bytes=96 * 1024, waves_per_group=8),
-    dict(automaton_bytes=48 * 1024, waves_per_group=4),
-    dict(automaton_bytes=48 * 1024, waves_per_group=8, chain_bytes=512),
+    dict(),  # library default (80 KiB automata, 8 waves, the plan's round size)
+    dict(automaton_bytes=48 * 1024),
+    dict(automaton_bytes=64 * 1024, line_bytes=64),
+    dict(automaton_bytes=24 * 1024, line_bytes=64),
+    dict(automaton_bytes=80 * 1024, waves_per_group=8, chain_bytes=512),
 ]
 
 _lock = threading.Lock()
@@ -185,7 +185,7 @@ def tune_merged(text, seg_off, patterns, pair_seg, pair_pat, reps: int = 2, forc
     built = {}
 
     def run_one(t):
-        k = (t.automaton_bytes, t.waves_per_group, t.chain_bytes)
+        k = (t.automaton_bytes, t.waves_per_group, t.chain_bytes, t.line_bytes)
         if k not in built:
             built[k] = api.MergedBatch(so, patterns, pair_seg, pair_pat, t, device=text.device)
         built[k].run(text)

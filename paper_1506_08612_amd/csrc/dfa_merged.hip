@@ -11,9 +11,12 @@
 // state and no automaton worth merging fits LDS, so each automaton is kept as
 // a byte-class map (256 entries; every byte that occurs in none of its
 // patterns is one class, on which every state returns to the start) and a
-// 16-bit table with one column per class.  A step is two LDS reads: the
-// class of the byte (independent of the state, so off the dependent chain)
-// and the next state.  Reporting states are numbered last (first_final on),
+// 16-bit table with one column per class.  A step is the class of the byte
+// (independent of the state, so off the dependent chain) and one LDS read of
+// the next state.  For DNA-like alphabets the class comes from registers (a
+// v_perm over an 8-entry table in two registers, four bytes at a time, see
+// reg_classes); other bytes take one more LDS read of the class map.
+// Reporting states are numbered last (first_final on),
 // so "is final" is one compare; visits of each reporting state are counted in
 // an LDS histogram and turned into per-pair counts at the end through the
 // per-state output lists.
@@ -36,11 +39,12 @@
 // unequal lengths exact, where a single m - 1 overlap (Sec. III.A) would count
 // some matches twice.
 //
-// Data movement is the single-pattern scan's: walks start on 128-byte
+// Data movement follows the single-pattern scan: walks start on 128-byte
 // boundaries (the first walk of a segment may start before the segment and
-// skips the bytes in front of it), 64-byte rounds whose two halves of each
-// line are requested back to back, a wave-private LDS transpose, and the
-// overlap taken from the neighbouring walk's staged first round.  Items are
+// skips the bytes in front of it), rounds of 32 or 64 bytes of every walk
+// staged through a wave-private LDS transpose (32-byte rounds take half the
+// LDS, so that a workgroup with a large automaton leaves room for another),
+// the overlap read from memory after the rounds.  Items are
 // ordered so that consecutive items on one XCD walk the same tile with
 // different automata, which keeps the tile in that XCD's L2.
 
@@ -60,12 +64,12 @@ namespace {
 
 using namespace dfa_dev;
 
-constexpr int kLine = 64;                        // bytes of every walk staged per round
+constexpr int kWavesPerSimd = 8;                 // register budget of the scan kernels (64 VGPRs)
 constexpr int kXcds = 8;                         // workgroups are dealt to the XCDs in turn
 constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 128)
 constexpr int64_t kMaxSpan = 1024;
 constexpr int kDefaultWaves = 8;
-constexpr int kDefaultAutomatonBytes = 48 * 1024;
+constexpr int kDefaultAutomatonBytes = 80 * 1024;
 constexpr int kMinAutomatonBytes = 4 * 1024;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kCmapBytes = 512;                  // 256 x u16: twice the class of each byte
@@ -74,11 +78,10 @@ typedef __attribute__((address_space(3))) const uint16_t lds_u16;
 
 // An automaton's LDS image (copied from the workspace to LDS address 0; its
 // visit counters follow it).  One-step automata: the nstates x ncls u16 table
-// at 0, then the 16-bit class map.  Pair automata (kPairMaps): two byte maps
-// at 0 and 256 (the first byte of a pair gives 2 ncls c, the second 2 c), the
-// nstates x ncls^2 u16 pair table at kPairMaps, the one-step table, then the
-// 16-bit class map, whose entries hold the one-step table's LDS offset plus
-// 2 c, so that one-step reads need no base either.
+// at 0, then the 16-bit class map.  Pair automata: a byte map of c at 0,
+// the nstates x ncls^2 u16 pair table at kPairMaps, the one-step table, then
+// the 16-bit class map, whose entries hold the one-step table's LDS offset
+// plus 2 c, so that one-step reads need no base either.
 struct MAuto {
     int64_t table_off;  // offset of the image in the workspace
     int64_t fin_base;   // global index of this automaton's first reporting state
@@ -89,7 +92,11 @@ struct MAuto {
     int32_t image_bytes;  // bytes of the image (16-byte multiple)
     int32_t cmap_off;     // LDS offset of the 16-bit class map
     int32_t pair;         // nonzero: pair automaton
-    int32_t pad;
+    int32_t cls_shift;    // register classes: a byte's slot is bits [s, s + 3) of it
+    uint32_t lut_lo;      // register classes: byte h of (lut_hi:lut_lo) is the class of the byte in slot h
+    uint32_t lut_hi;
+    uint32_t key_lo;      // byte h of (key_hi:key_lo): the one byte slot h's lut entry holds
+    uint32_t key_hi;
 };
 
 struct MItem {
@@ -130,22 +137,52 @@ struct MCtx {
     uint32_t hist;   // LDS address of the visit counters
     uint32_t F;      // first reporting state
     int64_t fin_base;
+    uint32_t cs, lut_lo, lut_hi, key_lo, key_hi;  // register classes (MAuto)
+    uint32_t wts0, wts1;  // pair automata: byte weights (ncls, 1) of each pair of a text word
 };
 
-// Pair automata: the byte maps sit at LDS 0 and 256 and the pair table at
-// kPairMaps, so every address of a pair step is a sum of per-lane terms and a
-// constant the reads take as their offset.  A pair entry is the state after
-// both bytes, with bit 15 set when the state after the first byte reports
-// (states stay below 2^15).
-constexpr uint32_t kPairMaps = 512;
+// Pair automata: the byte map sits at LDS 0 and the pair table at kPairMaps,
+// so every address of a pair step is a sum of per-lane terms and a constant
+// the reads take as their offset.  A pair entry is the state after both
+// bytes, with bit 15 set when the state after the first byte reports (states
+// stay below 2^15).
+constexpr uint32_t kPairMaps = 256;
 constexpr uint32_t kMidReports = 0x8000u;
 typedef __attribute__((address_space(3))) const uint8_t lds_u8c;
 
-// One automaton step: class of byte c (the map holds twice the class), then
-// the next state.
-__device__ __forceinline__ uint32_t mstep(uint32_t q, uint32_t c, const MCtx &x) {
-    const uint32_t k2 = *reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * c));
-    return *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2));
+// Register classes.  Where an automaton's pattern bytes (those of classes 1
+// and up) are at most eight and differ in three consecutive bits [s, s + 3),
+// those bits of a text byte name its slot, and one v_perm over the 8-byte
+// register table (lut_hi:lut_lo) gives the class c of all four bytes of a word
+// at once; the same v_perm over (key_hi:key_lo) gives the byte each slot
+// stands for.  A word whose four bytes equal their slots' bytes is classed in
+// registers; any other word (a default-class byte in a slot that stands for
+// another byte) takes the LDS class map.  Slots that no pattern byte takes
+// stand for a default-class byte ('N' where it can), with c = 0.  An
+// automaton whose pattern bytes do not fit has keys that no byte matches.
+__device__ __forceinline__ bool reg_classes(uint32_t w, const MCtx &x, uint32_t &P) {
+    const uint32_t h = (w >> x.cs) & 0x07070707u;
+    P = __builtin_amdgcn_perm(x.lut_hi, x.lut_lo, h);
+    return __builtin_amdgcn_perm(x.key_hi, x.key_lo, h) == w;
+}
+
+// The classes of the four bytes of w, byte b of the result for byte b of w:
+// from registers, else from the LDS maps (pair automata: the byte map of c at
+// 0; one-step automata: the 16-bit map of 2 c, their table being at 0).
+template <bool PAIR>
+__device__ __forceinline__ uint32_t word_classes(uint32_t w, const MCtx &x) {
+    uint32_t P;
+    if (!reg_classes(w, x, P)) {
+        P = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t byte = (w >> (8 * b)) & 0xffu;
+            const uint32_t c = PAIR ? uint32_t(*reinterpret_cast<lds_u8c *>(uintptr_t(byte)))
+                                    : uint32_t(*reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * byte))) >> 1;
+            P |= c << (8 * b);
+        }
+    }
+    return P;
 }
 
 // A reporting state reached at byte j of the overlap: count each reported
@@ -159,19 +196,15 @@ __device__ __forceinline__ void overlap_hit(const MParams &p, const MCtx &x, uin
     }
 }
 
-// Walk 16 bytes; byte b of word w is byte jb + 4w + b of the walk.  Without
-// GUARD every byte is inside the lane's own span (full waves); with GUARD the
-// lane's [lo, own, len) decide.
-template <bool GUARD>
-__device__ __forceinline__ void mwalk16(const v4u &t, uint32_t &q, uint32_t jb, const MCtx &x, const MLane &L,
-                                        unsigned char *smem, const MParams &p) {
+// Walk 16 bytes one byte per step with the lane's [lo, own, len) deciding
+// (edge waves and every overlap); byte b of word w is byte jb + 4w + b of the
+// walk.  Per half of the unit: its 8 byte classes first (they do not depend
+// on the state, so their reads are in flight together), then the 8 steps,
+// which keep only the transition read on the state chain, then the visits of
+// the states reached (their counter updates off the chain).
+__device__ __forceinline__ void mwalk16_guarded(const v4u &t, uint32_t &q, uint32_t jb, const MCtx &x,
+                                                const MLane &L, unsigned char *smem, const MParams &p) {
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
-    // Per half of the unit: its 8 byte classes first (they do not depend on
-    // the state, so their reads are in flight together), then the 8 steps,
-    // which keep only the transition read on the state chain, then the
-    // visits of the states reached (their counter updates off the chain).
-    // Halves rather than the whole unit: 16 of each would cost 16 more
-    // registers, i.e. resident waves where the automata are small.
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         uint32_t k2[8], qs[8];
@@ -182,18 +215,42 @@ __device__ __forceinline__ void mwalk16(const v4u &t, uint32_t &q, uint32_t jb, 
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2[i]));
-            if (GUARD && jb + uint32_t(8 * h + i) < L.lo) q = 0;  // in front of the segment: stay in the start state
+            if (jb + uint32_t(8 * h + i) < L.lo) q = 0;  // in front of the segment: stay in the start state
             qs[i] = q;
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint32_t j = jb + uint32_t(8 * h + i);
             if (qs[i] >= x.F) {
-                if (!GUARD || j < L.own)
+                if (j < L.own)
                     atomicAdd(hist + (qs[i] - x.F), 1u);
                 else if (j < L.len)
                     overlap_hit(p, x, qs[i], j, L.own);
             }
+        }
+    }
+}
+
+// Walk 16 bytes of a full wave one byte per step (one-step automata).  Per
+// text word: the classes of its bytes, then its 4 steps, which keep only the
+// transition read on the state chain, then one test of the largest state
+// reached against F (reporting states are numbered last) before the visits
+// are counted.
+__device__ __forceinline__ void mwalk16_full(const v4u &t, uint32_t &q, const MCtx &x, uint32_t *hist) {
+#pragma unroll
+    for (int wd = 0; wd < 4; ++wd) {
+        const uint32_t P = word_classes<false>(t[wd], x);
+        uint32_t qs[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k2 = ((P << 1) >> (8 * i)) & 0x1feu;  // 2 c of byte i
+            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2));
+            qs[i] = q;
+        }
+        if (max(max(qs[0], qs[1]), max(qs[2], qs[3])) >= x.F) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (qs[i] >= x.F) atomicAdd(hist + (qs[i] - x.F), 1u);
         }
     }
 }
@@ -211,23 +268,22 @@ __device__ __forceinline__ void pair_visits(uint32_t e, uint32_t qp, uint32_t c1
     if (q >= x.F) atomicAdd(hist + (q - x.F), 1u);
 }
 
-// Walk 16 bytes of a full wave two bytes per step with a pair automaton: per
-// text word (4 bytes), the byte maps of its bytes, then 2 dependent pair
-// reads, then one test of the larger entry against F (reporting states are
-// numbered last, and bit 15 exceeds every state).
-__device__ __forceinline__ void mwalk16_pair(const v4u &t, uint32_t &q, const MCtx &x, unsigned char *smem) {
-    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
+// Walk 16 bytes of a full wave two bytes per step (pair automata).  Per text
+// word: the classes of its bytes, then 2 dependent pair reads, each at row q
+// and column ncls c1 + c2 (a v_dot4 of the word's class bytes with weights
+// 2 ncls and 2 gives the byte offset), then one test of the larger entry
+// against F (bit 15 exceeds every state).
+__device__ __forceinline__ void mwalk16_pair(const v4u &t, uint32_t &q, const MCtx &x, uint32_t *hist) {
 #pragma unroll
     for (int wd = 0; wd < 4; ++wd) {
         const uint32_t w = t[wd];
-        const uint32_t a0 = *reinterpret_cast<lds_u8c *>(uintptr_t(w & 0xffu));
-        const uint32_t b0 = *reinterpret_cast<lds_u8c *>(uintptr_t(256u + ((w >> 8) & 0xffu)));
-        const uint32_t a1 = *reinterpret_cast<lds_u8c *>(uintptr_t((w >> 16) & 0xffu));
-        const uint32_t b1 = *reinterpret_cast<lds_u8c *>(uintptr_t(256u + (w >> 24)));
+        const uint32_t P = word_classes<true>(w, x);
         const uint32_t q0 = q;
-        const uint32_t e0 = *reinterpret_cast<lds_u16 *>(uintptr_t(kPairMaps + __umul24(q, x.rowp) + a0 + b0));
+        const uint32_t e0 = *reinterpret_cast<lds_u16 *>(
+            uintptr_t(kPairMaps + __builtin_amdgcn_udot4(P, x.wts0, __umul24(q, x.rowp), false)));
         const uint32_t q1 = e0 & (kMidReports - 1u);
-        const uint32_t e1 = *reinterpret_cast<lds_u16 *>(uintptr_t(kPairMaps + __umul24(q1, x.rowp) + a1 + b1));
+        const uint32_t e1 = *reinterpret_cast<lds_u16 *>(
+            uintptr_t(kPairMaps + __builtin_amdgcn_udot4(P, x.wts1, __umul24(q1, x.rowp), false)));
         q = e1 & (kMidReports - 1u);
         if (max(e0, e1) >= x.F) {
             if (e0 >= x.F) pair_visits(e0, q0, w & 0xffu, x, hist);
@@ -236,72 +292,69 @@ __device__ __forceinline__ void mwalk16_pair(const v4u &t, uint32_t &q, const MC
     }
 }
 
-// The four units of a staged round, the next one read from LDS while the
-// current one is walked.
-template <bool GUARD, bool PAIR = false>
-__device__ __forceinline__ void mwalk_round(const v4u *xb, int lane, uint32_t &q, uint32_t rb, const MCtx &x,
-                                            const MLane &L, unsigned char *smem, const MParams &p) {
-    using G = Geo<kLine>;
-    v4u cur = unit_of<kLine>(xb, 0, lane, 0), nxt = cur;
+// The units of a staged round of a full wave, the next one read from LDS
+// while the current one is walked.
+template <int LINE, bool PAIR>
+__device__ __forceinline__ void mwalk_round(const v4u *xb, int lane, uint32_t &q, const MCtx &x, uint32_t *hist) {
+    using G = Geo<LINE>;
+    v4u cur = unit_of<LINE>(xb, 0, lane, 0), nxt = cur;
 #pragma unroll
     for (int u = 0; u < G::U; ++u) {
-        if (u + 1 < G::U) nxt = unit_of<kLine>(xb, 0, lane, u + 1);
+        if (u + 1 < G::U) nxt = unit_of<LINE>(xb, 0, lane, u + 1);
         if (PAIR)
-            mwalk16_pair(cur, q, x, smem);
+            mwalk16_pair(cur, q, x, hist);
         else
-            mwalk16<GUARD>(cur, q, rb + 16u * u, x, L, smem, p);
+            mwalk16_full(cur, q, x, hist);
         cur = nxt;
     }
 }
 
 // The rounds and overlap of a full wave (every walk inside its segment, its
 // span owned and its overlap inside the segment and the text).  S is a
-// multiple of 128: R is even and every round is whole.  PAIR: the rounds go
-// two bytes per step; the overlap always goes one byte per step (it counts
-// only matches that start inside the span).
-template <int H, bool PAIR>
-__device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, int64_t wbase, int64_t wstart, int64_t S,
-                                          uint32_t lane_off, int maxm, uint32_t &q, const MCtx &x, const MLane &L,
-                                          unsigned char *smem) {
-    using G = Geo<kLine>;
-    const int R = int(S / kLine);
+// multiple of 128: the rounds come in pairs.  The overlap goes one byte per
+// step (it counts only matches that start inside the span), its units read
+// from memory after the rounds: the first H unrolled, the rest in a loop.
+template <int H, bool PAIR, int LINE>
+__device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, int64_t wbase, int64_t wstart,
+                                          int64_t S, uint32_t lane_off, int maxm, uint32_t &q, const MCtx &x,
+                                          const MLane &L, unsigned char *smem) {
+    using G = Geo<LINE>;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + x.hist);
+    const int R = int(S / LINE);
     const int rlast = R - 1;
     const uint32_t off_none = 16u * uint32_t(lane % G::U);
-    const int hu = (maxm - 1 + 15) / 16;
-    v4u pa[1][G::U], pb[1][G::U], halo[1][H];
-    fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 0, rlast);
-    fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 1, rlast);
-    stage_round<1, kLine>(pa, xb, lane);
-    grab_halo<1, kLine, H>(halo, xb, lane, p.text, wbase, S, hu, G::U);
-    mwalk_round<false, PAIR>(xb, lane, q, 0u, x, L, smem, p);
-    stage_round<1, kLine>(pb, xb, lane);
-    fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 2, rlast);
-    fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 3, rlast);
-    mwalk_round<false, PAIR>(xb, lane, q, uint32_t(kLine), x, L, smem, p);
-    for (int r = 2; r < R; r += 2) {
-        stage_round<1, kLine>(pa, xb, lane);
-        mwalk_round<false, PAIR>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
-        stage_round<1, kLine>(pb, xb, lane);
-        fetch_round_or_none<1, kLine>(pa, p.text, wbase, S, lane_off, lane_off, off_none, r + 2, rlast);
-        fetch_round_or_none<1, kLine>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
-        mwalk_round<false, PAIR>(xb, lane, q, uint32_t((r + 1) * kLine), x, L, smem, p);
+    v4u pa[1][G::U], pb[1][G::U];
+    fetch_round_or_none<1, LINE>(pa, p.text, wbase, S, lane_off, lane_off, off_none, 0, rlast);
+    fetch_round_or_none<1, LINE>(pb, p.text, wbase, S, lane_off, lane_off, off_none, 1, rlast);
+    for (int r = 0; r < R; r += 2) {
+        stage_round<1, LINE>(pa, xb, lane);
+        mwalk_round<LINE, PAIR>(xb, lane, q, x, hist);
+        stage_round<1, LINE>(pb, xb, lane);
+        fetch_round_or_none<1, LINE>(pa, p.text, wbase, S, lane_off, lane_off, off_none, r + 2, rlast);
+        fetch_round_or_none<1, LINE>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
+        mwalk_round<LINE, PAIR>(xb, lane, q, x, hist);
     }
-    // the overlap: its first H units from registers, the rest from memory
+    const int hu = (maxm - 1 + 15) / 16;
+    const uint8_t *ov = p.text + wstart + S;
+    v4u halo[H];
 #pragma unroll
     for (int u = 0; u < H; ++u)
-        if (u < hu) mwalk16<true>(halo[0][u], q, uint32_t(S) + 16u * u, x, L, smem, p);
+        if (u < hu) halo[u] = *reinterpret_cast<const v4u *>(ov + 16 * u);
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+        if (u < hu) mwalk16_guarded(halo[u], q, uint32_t(S) + 16u * u, x, L, smem, p);
     for (int u = H; u < hu; ++u) {
-        const v4u t = *reinterpret_cast<const v4u *>(p.text + wstart + S + 16 * u);
-        mwalk16<true>(t, q, uint32_t(S) + 16u * u, x, L, smem, p);
+        const v4u t = *reinterpret_cast<const v4u *>(ov + 16 * u);
+        mwalk16_guarded(t, q, uint32_t(S) + 16u * u, x, L, smem, p);
     }
 }
 
 // PAIR: every item's automaton is a pair automaton (the plan puts those items
-// first and launches them apart, so that each kernel keeps only its own path's
-// registers).
-template <int H, bool PAIR>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_merged(MParams p) {
-    using G = Geo<kLine>;
+// in launches of their own, so that each kernel keeps only its own path's
+// registers).  LINE: bytes of every walk staged per round (32 or 64).
+template <int H, bool PAIR, int LINE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd))) void k_merged(MParams p) {
+    using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     const MItem it = p.items[blockIdx.x];
     const MAuto au = p.autos[it.automaton];
@@ -322,8 +375,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
     x.hist = ib;
     x.F = F;
     x.fin_base = au.fin_base;
+    x.cs = uint32_t(__builtin_amdgcn_readfirstlane(au.cls_shift));
+    x.lut_lo = uint32_t(__builtin_amdgcn_readfirstlane(int(au.lut_lo)));
+    x.lut_hi = uint32_t(__builtin_amdgcn_readfirstlane(int(au.lut_hi)));
+    x.key_lo = uint32_t(__builtin_amdgcn_readfirstlane(int(au.key_lo)));
+    x.key_hi = uint32_t(__builtin_amdgcn_readfirstlane(int(au.key_hi)));
+    x.wts0 = (2u * ncls) | (2u << 8);
+    x.wts1 = (2u * ncls << 16) | (2u << 24);
     const uint32_t stage = (x.hist + 4u * nfin + 15u) & ~15u;
-    v4u *xb = reinterpret_cast<v4u *>(smem + stage + wave * (kWave * kLine));
+    v4u *xb = reinterpret_cast<v4u *>(smem + stage + wave * (kWave * LINE));
     {
         const v4u *src = reinterpret_cast<const v4u *>(p.ws + au.table_off);
         const uint32_t chunks = ib / 16u;
@@ -352,21 +412,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
     uint32_t q = 0;
     const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(S) + 16u * uint32_t(lane % G::U);
-    const int rounds_all = int((S + maxm - 1 + kLine - 1) / kLine);
+    const int rounds_all = int((S + maxm - 1 + LINE - 1) / LINE);
     const int64_t wlast = wbase + int64_t(kWave - 1) * S;
     const bool full = wbase >= it.seg_lo && wlast + S <= it.own_end && wlast + S + maxm - 1 <= it.seg_end &&
-                      wlast + int64_t(rounds_all) * kLine <= p.n;
+                      wlast + int64_t(rounds_all) * LINE <= p.n;
 
     if (full) {
-        walk_full<H, PAIR>(p, xb, lane, wbase, wstart, S, lane_off, maxm, q, x, L, smem);
+        walk_full<H, PAIR, LINE>(p, xb, lane, wbase, wstart, S, lane_off, maxm, q, x, L, smem);
     } else {
-        // edge waves: the segment's first or last walks, or the text's end
+        // edge waves (the segment's first or last walks, or the text's end): one byte per step
         v4u pf[1][G::U];
-        fetch_round<1, kLine, true>(pf, p.text, p.n, wbase, S, lane_off, 0);
+        fetch_round<1, LINE, true>(pf, p.text, p.n, wbase, S, lane_off, 0);
         for (int r = 0; r < rounds_all; ++r) {
-            stage_round<1, kLine>(pf, xb, lane);
-            if (r + 1 < rounds_all) fetch_round<1, kLine, true>(pf, p.text, p.n, wbase, S, lane_off, r + 1);
-            mwalk_round<true>(xb, lane, q, uint32_t(r * kLine), x, L, smem, p);
+            stage_round<1, LINE>(pf, xb, lane);
+            if (r + 1 < rounds_all) fetch_round<1, LINE, true>(pf, p.text, p.n, wbase, S, lane_off, r + 1);
+#pragma unroll
+            for (int u = 0; u < G::U; ++u)
+                mwalk16_guarded(unit_of<LINE>(xb, 0, lane, u), q, uint32_t(r * LINE + 16 * u), x, L, smem, p);
         }
     }
 
@@ -406,11 +468,16 @@ __global__ void k_visits_to_counts(const unsigned long long *visits, const int32
 
 using dfa::hip_ok;
 
-const void *merged_fn(int H, bool pair) {
-    if (H == 1) return pair ? reinterpret_cast<const void *>(&k_merged<1, true>)
-                            : reinterpret_cast<const void *>(&k_merged<1, false>);
-    return pair ? reinterpret_cast<const void *>(&k_merged<4, true>)
-                : reinterpret_cast<const void *>(&k_merged<4, false>);
+template <int LINE>
+const void *merged_fn_line(int H, bool pair) {
+    if (H == 1) return pair ? reinterpret_cast<const void *>(&k_merged<1, true, LINE>)
+                            : reinterpret_cast<const void *>(&k_merged<1, false, LINE>);
+    return pair ? reinterpret_cast<const void *>(&k_merged<4, true, LINE>)
+                : reinterpret_cast<const void *>(&k_merged<4, false, LINE>);
+}
+
+const void *merged_fn(int H, bool pair, int line) {
+    return line == 64 ? merged_fn_line<64>(H, pair) : merged_fn_line<32>(H, pair);
 }
 
 struct MHostPlan {
@@ -420,6 +487,7 @@ struct MHostPlan {
     std::vector<OutEntry> out_ent;
     std::vector<uint8_t> area;  // tables and class maps
     int waves = kDefaultWaves;
+    int line = 0;  // bytes of every walk staged per round (0: the plan chooses)
     int H = 1;
     int lds = 0;  // dynamic LDS of the largest launch
     // launch groups (pair automata needing at most a third, a half, all of a
@@ -435,9 +503,10 @@ struct MHostPlan {
     int budget = kDefaultAutomatonBytes;
 };
 
-// Pair automata: at most kPairMaxCls byte classes (the first byte's map entry,
-// 2 ncls c, must fit a byte), states below 2^15, every image offset below 64
-// KiB (the 16-bit class map holds the one-step table's offset).
+// Pair automata: at most kPairMaxCls byte classes (a state's row of ncls^2
+// entries grows fast; the byte map's 2 c and the weight ncls of a pair's
+// column sum are bytes), states below 2^15, every image offset below 64 KiB
+// (the 16-bit class map holds the one-step table's offset).
 constexpr int kPairMaxCls = 11;
 
 int64_t auto_lds_bytes(const MAuto &a) {
@@ -449,14 +518,70 @@ int64_t auto_lds_bytes(const MAuto &a) {
 constexpr int64_t kLdsBlock = 2048;
 
 // Workgroups that fit a CU when each needs `need` bytes of LDS (by LDS, and
-// by registers: the kernels keep 6 waves per SIMD, 24 per CU).
+// by registers: kWavesPerSimd per SIMD, 4 SIMDs per CU).
 int64_t groups_for(int64_t need, int waves) {
     const int64_t by_lds = kLdsPerCu / dfa::round_up(need, kLdsBlock);
-    return std::max<int64_t>(1, std::min<int64_t>(by_lds, 24 / waves));
+    return std::max<int64_t>(1, std::min<int64_t>(by_lds, 4 * kWavesPerSimd / waves));
 }
 
+// LDS of one wave's transpose buffer: a round of each of its 64 walks
+int64_t stage_bytes_per_wave(int line) { return int64_t(kWave) * line; }
+
 // ... with an automaton of `bytes` plus one transpose buffer per wave
-int64_t groups_per_cu(int64_t bytes, int waves) { return groups_for(bytes + int64_t(waves) * kWave * kLine, waves); }
+int64_t groups_per_cu(int64_t bytes, int waves, int line) {
+    return groups_for(bytes + int64_t(waves) * stage_bytes_per_wave(line), waves);
+}
+
+// Register classes of an automaton (the device side's reg_classes): the
+// first shift s that gives its pattern bytes distinct slots, preferring one
+// where 'N' (an assembly gap, of the default class unless a pattern holds it)
+// gets a slot of its own; else keys that no byte matches.
+void set_reg_classes(const dfa::AcAutomaton &a, MAuto &m) {
+    std::vector<int> pb;
+    for (int b = 0; b < 256; ++b)
+        if (a.cls[b]) pb.push_back(b);
+    auto slot = [](int b, int s) { return (b >> s) & 7; };
+    int shift = -1;
+    for (int pass = 0; pass < 2 && shift < 0 && pb.size() <= 8; ++pass)
+        for (int s = 0; s <= 5 && shift < 0; ++s) {
+            unsigned seen = 0;
+            bool ok = true;
+            for (int b : pb) {
+                ok = ok && !((seen >> slot(b, s)) & 1u);
+                seen |= 1u << slot(b, s);
+            }
+            if (ok && (pass == 1 || a.cls['N'] || !((seen >> slot('N', s)) & 1u))) shift = s;
+        }
+    uint8_t lut[8] = {}, key[8] = {};
+    if (shift < 0) {
+        m.cls_shift = 0;
+        for (int h = 0; h < 8; ++h) key[h] = uint8_t((h + 1) & 7);  // slot of key[h] is not h: never equal
+    } else {
+        m.cls_shift = shift;
+        bool used[8] = {};
+        for (int b : pb) {
+            key[slot(b, shift)] = uint8_t(b);
+            lut[slot(b, shift)] = uint8_t(a.cls[b]);
+            used[slot(b, shift)] = true;
+        }
+        for (int h = 0; h < 8; ++h) {
+            if (used[h]) continue;
+            int pick = -1;
+            for (int b : {int('N'), int('n')})
+                if (pick < 0 && slot(b, shift) == h && !a.cls[b]) pick = b;
+            for (int b = 0; b < 256 && pick < 0; ++b)
+                if (slot(b, shift) == h && !a.cls[b]) pick = b;
+            key[h] = uint8_t(pick);  // a default-class byte: c = 0
+        }
+    }
+    auto pack = [](const uint8_t *v) {
+        return uint32_t(v[0]) | uint32_t(v[1]) << 8 | uint32_t(v[2]) << 16 | uint32_t(v[3]) << 24;
+    };
+    m.lut_lo = pack(lut);
+    m.lut_hi = pack(lut + 4);
+    m.key_lo = pack(key);
+    m.key_hi = pack(key + 4);
+}
 
 int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const uint8_t *patterns,
                   const int64_t *pat_off, const int32_t *pat_len, MHostPlan &hp) {
@@ -479,6 +604,7 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     m.first_final = a.first_final;
     m.ncls = a.ncls;
     m.maxm = maxm;
+    set_reg_classes(a, m);
     m.table_off = int64_t(hp.area.size());
     m.fin_base = int64_t(hp.out_off.size()) - 1;
     const int64_t ns = a.nstates, nc = a.ncls;
@@ -489,18 +615,12 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     const bool pair_ok = hp.allow_pair && nc <= kPairMaxCls && ns < int64_t(kMidReports) &&
                          pair_image + hist <= hp.budget && pair_image <= 65536;
     // A pair automaton halves the dependent table reads per byte of a full
-    // wave's rounds, but its larger image may leave room for fewer workgroups
-    // per CU.  Measured (segments of 1 kB - 250 MB with 1-16 patterns of 6-48
-    // bytes, and 72 8-mers over 1 GB): at equal workgroups per CU a pair
-    // automaton walks a segment ~15 % faster; with one workgroup fewer it is
-    // slower, except where the patterns are short (up to 17 bytes: the overlap
-    // walked one byte per step is short too), where two pair workgroups beat
-    // three one-step ones by ~7 %.  Taken on that evidence, or always when the
-    // plan packs for pairs.
-    const int64_t one_image = one + kCmapBytes;
-    const int64_t g_pair = groups_per_cu(pair_image + hist, hp.waves);
-    const int64_t g_one = groups_per_cu(one_image + hist, hp.waves);
-    m.pair = pair_ok && (hp.pack_pairs || g_pair >= g_one || (maxm <= 17 && g_pair >= 2 && g_pair + 1 >= g_one));
+    // wave's rounds, but at the occupancy the one-step kernel reaches (8 waves
+    // per SIMD, classes from registers) it was slower everywhere measured:
+    // 2000 segments of 1 kB - 250 MB with 1-16 patterns of 6-48 bytes, 0.56
+    // ms against 0.45 ms one-step; 72 8-mers over 1 GB, 0.32 against 0.30 ms.
+    // Taken only when the plan asks for two bytes per step.
+    m.pair = pair_ok && hp.pack_pairs;
     const int64_t tab1 = m.pair ? int64_t(kPairMaps) + pairs : 0;  // LDS offset of the one-step table
     m.cmap_off = int32_t(tab1 + one);
     m.image_bytes = int32_t(tab1 + one + kCmapBytes);
@@ -511,12 +631,9 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     uint16_t *cm = reinterpret_cast<uint16_t *>(img + m.cmap_off);
     for (int b = 0; b < 256; ++b) cm[b] = uint16_t(tab1 + 2 * a.cls[b]);
     if (m.pair) {
-        // byte maps: 2 ncls c for a pair's first byte, 2 c for its second; entry
-        // (q, c1 c2) = the state after both bytes, bit 15 if the one after c1 reports
-        for (int b = 0; b < 256; ++b) {
-            img[b] = uint8_t(2 * nc * a.cls[b]);
-            img[256 + b] = uint8_t(2 * a.cls[b]);
-        }
+        // byte map: c; entry (q, c1 c2) = the state after both bytes, bit 15
+        // if the one after c1 reports
+        for (int b = 0; b < 256; ++b) img[b] = uint8_t(a.cls[b]);
         uint16_t *pt = reinterpret_cast<uint16_t *>(img + kPairMaps);
         for (int64_t q = 0; q < ns; ++q)
             for (int64_t c1 = 0; c1 < nc; ++c1) {
@@ -584,6 +701,11 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
             dfa::set_error("tune.step_bytes=%d must be 1 or 2 (or 0)", t->step_bytes);
             return DFA_EINVAL;
         }
+        if (t->line_bytes != 0 && t->line_bytes != 32 && t->line_bytes != 64) {
+            dfa::set_error("tune.line_bytes=%d: merged scans take 32 or 64 (or 0)", t->line_bytes);
+            return DFA_EINVAL;
+        }
+        if (t->line_bytes) hp.line = t->line_bytes;
         if (t->step_bytes == 1) hp.allow_pair = false;
         if (t->step_bytes == 2) hp.pack_pairs = true;
         if (t->waves_per_group < 0 || t->waves_per_group > 8) {
@@ -654,10 +776,14 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         // add patterns while the trie (counted incrementally from the common
         // prefix with the previous pattern) fits the budget
         // LDS per state: one-step table row and visit counter, and with pair
-        // packing the pair table row too (plus the two byte maps per automaton)
+        // packing the pair table row too (plus the byte map per automaton);
+        // a pair automaton's image (without its counters) stays below 64 KiB
         const bool pp = hp.pack_pairs && ncls <= kPairMaxCls;
         const int64_t per_state = 2 * ncls + 4 + (pp ? 2 * ncls * ncls : 0);
         const int64_t fixed = kCmapBytes + (pp ? int64_t(kPairMaps) : 0);
+        const int64_t pack_budget = pp ? std::min<int64_t>(budget, (65536 - 32 - fixed) / (per_state - 4) *
+                                                                       per_state + fixed)
+                                       : budget;
         const size_t a_first = hp.autos.size();
         std::vector<int64_t> cur;
         int64_t states = 1;
@@ -671,7 +797,8 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
                 while (common < n && patterns[pat_off[j] + common] == patterns[pat_off[jp] + common]) ++common;
             }
             const int64_t add = pat_len[j] - common;
-            if (!cur.empty() && ((states + add) * per_state + fixed > budget || states + add > DFA_AC_MAX_STATES)) {
+            if (!cur.empty() &&
+                ((states + add) * per_state + fixed > pack_budget || states + add > DFA_AC_MAX_STATES)) {
                 const int rc = add_automaton(cur, pair_pat, patterns, pat_off, pat_len, hp);
                 if (rc != DFA_OK) return rc;
                 cur.clear();
@@ -687,14 +814,27 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         seg_autos.emplace_back(a_first, hp.autos.size());
     }
     hp.H = maxm_all <= 17 ? 1 : 4;
-    int64_t auto_max = 0, one_max = 0, pair_max = 0;
-    for (const MAuto &a : hp.autos) {
-        auto_max = std::max(auto_max, auto_lds_bytes(a));
-        (a.pair ? pair_max : one_max) = std::max(a.pair ? pair_max : one_max, auto_lds_bytes(a));
+    int64_t auto_max = 0;
+    for (const MAuto &a : hp.autos) auto_max = std::max(auto_max, auto_lds_bytes(a));
+    if (!hp.line) {
+        // 64-byte rounds (whole halves of a line per load: the faster reads)
+        // unless 32-byte rounds, whose transpose buffers take half the LDS,
+        // fit more workgroups per CU, weighting each automaton by the bytes it
+        // walks (1 GB x 1024 patterns in 48 KiB automata: 2.5 ms with 32-byte
+        // rounds and 3 workgroups per CU against 3.3 ms with 64 and 2)
+        double occ[2] = {0, 0};
+        for (size_t oi = 0; oi < order.size(); ++oi) {
+            const double len = double(seg_off[order[oi] + 1] - seg_off[order[oi]]);
+            for (size_t a = seg_autos[oi].first; a < seg_autos[oi].second; ++a)
+                for (int l = 0; l < 2; ++l)
+                    occ[l] += len * double(groups_per_cu(auto_lds_bytes(hp.autos[a]), hp.waves, 32 << l));
+        }
+        hp.line = occ[0] > occ[1] ? 32 : 64;
     }
     // fewer waves per workgroup if the largest automaton leaves too little room
-    while (hp.waves > 1 && auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) --hp.waves;
-    if (auto_max + int64_t(hp.waves) * kWave * kLine > kLdsPerCu) {
+    const int64_t per_wave = stage_bytes_per_wave(hp.line);
+    while (hp.waves > 1 && auto_max + int64_t(hp.waves) * per_wave > kLdsPerCu) --hp.waves;
+    if (auto_max + int64_t(hp.waves) * per_wave > kLdsPerCu) {
         dfa::set_error("dfa_merged: an automaton needs %lld bytes of LDS", (long long)auto_max);
         return DFA_EINVAL;
     }
@@ -735,14 +875,14 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         return DFA_EINVAL;
     }
     // launch groups, each with the LDS its largest automaton needs: pair
-    // automata by how many workgroups per CU they leave room for (3, 2, 1),
-    // then the one-step ones; items keep their order inside a group
-    const int64_t staging = int64_t(hp.waves) * kWave * kLine;
+    // automata by how many workgroups per CU they leave room for (4 or more,
+    // 3, 2, 1), then the one-step ones the same way; items keep their order
+    // inside a group
+    const int64_t staging = int64_t(hp.waves) * per_wave;
     auto group_of = [&](const MItem &it) {
         const MAuto &a = hp.autos[size_t(it.automaton)];
-        if (!a.pair) return DFA_MERGED_GROUPS - 1;
         const int64_t g = groups_for(auto_lds_bytes(a) + staging, hp.waves);
-        return g >= 3 ? 0 : g == 2 ? 1 : 2;
+        return (a.pair ? 0 : DFA_MERGED_GROUPS / 2) + (g >= 4 ? 0 : 4 - int(g));
     };
     std::stable_sort(hp.items.begin(), hp.items.end(),
                      [&](const MItem &x, const MItem &y) { return group_of(x) < group_of(y); });
@@ -752,8 +892,6 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         hp.group_lds[g] = std::max(hp.group_lds[g], int(auto_lds_bytes(hp.autos[size_t(it.automaton)]) + staging));
     }
     hp.lds = int(auto_max + staging);
-    (void)one_max;
-    (void)pair_max;
     return DFA_OK;
 }
 
@@ -809,10 +947,11 @@ extern "C" int dfa_merged_prepare(const int64_t *seg_off, int32_t nseg, const ui
     plan->waves_per_group = hp.waves;
     plan->lds_bytes = hp.lds;
     plan->reserved[0] = hp.H;
+    plan->reserved[1] = hp.line;
     for (int g = 0; g < DFA_MERGED_GROUPS; ++g) {
         plan->group_items[g] = hp.group_items[g];
         plan->group_lds[g] = hp.group_lds[g];
-        plan->group_pair[g] = g < DFA_MERGED_GROUPS - 1 ? 1 : 0;
+        plan->group_pair[g] = g < DFA_MERGED_GROUPS / 2 ? 1 : 0;
     }
     if (!workspace) {
         dfa::clear_error();
@@ -863,13 +1002,14 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
         return DFA_EINVAL;
     }
     const int H = plan->reserved[0];
+    const int line = plan->reserved[1];
     int64_t grouped = 0;
     bool groups_ok = true;
     for (int g = 0; g < DFA_MERGED_GROUPS; ++g) {
         groups_ok &= plan->group_items[g] >= 0 && plan->group_lds[g] >= 0 && plan->group_lds[g] <= kLdsPerCu;
         grouped += plan->group_items[g];
     }
-    if ((H != 1 && H != 4) || plan->waves_per_group < 1 || plan->waves_per_group > 8 || plan->lds_bytes < 0 ||
+    if ((H != 1 && H != 4) || (line != 32 && line != 64) || plan->waves_per_group < 1 || plan->waves_per_group > 8 || plan->lds_bytes < 0 ||
         plan->lds_bytes > kLdsPerCu || !groups_ok || grouped != plan->nitems) {
         dfa::set_error("dfa_merged_run: plan not made by dfa_merged_prepare");
         return DFA_EINVAL;
@@ -902,7 +1042,7 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
     for (int64_t g = 0, first = 0; g < DFA_MERGED_GROUPS; first += plan->group_items[g], ++g) {
         const int64_t count = plan->group_items[g];
         if (count == 0) continue;
-        const void *fn = merged_fn(H, plan->group_pair[g] != 0);
+        const void *fn = merged_fn(H, plan->group_pair[g] != 0, line);
         if (!dfa::allow_lds(fn, kLdsPerCu)) return DFA_EHIP;
         MParams kp = mp;
         kp.items = mp.items + first;

@@ -106,6 +106,7 @@ def test_merged_prepare_argument_checks():
         ([0, 1000], pats, [0], [0], api.tune(chain_bytes=192)),  # span not a multiple of 128
         ([0, 1000], pats, [0], [0], api.tune(automaton_bytes=1000)),
         ([0, 1000], pats, [0], [0], api.tune(waves_per_group=9)),
+        ([0, 1000], pats, [0], [0], api.tune(line_bytes=128)),    # rounds of 32 or 64 bytes only
         ([0, 1000], [b""], [0], [0], None),                     # empty pattern
         ([0, 1000], [b"A" * 256], [0], [0], None),              # too long
     ]
@@ -188,14 +189,16 @@ def test_merged_decomposition_model_matches_oracle(seed):
 
 
 def test_merged_prepare_pair_automata():
-    """Pair automata (two bytes per step): small automata over few byte classes take
-    them by default, step_bytes=1 turns them off, step_bytes=2 packs patterns so that
-    every automaton fits as one, and their items are planned first."""
+    """Pair automata (two bytes per step): only when step_bytes=2 asks for them (one
+    byte per step is the default and step_bytes=1), packing patterns so that every
+    automaton fits as one; their items are planned first."""
     rng = np.random.default_rng(6)
     pats = _random_set(rng, 6, 6, 12)
     n = len(pats)
     _, dflt = _prepare([0, 1 << 20], pats, [0] * n, list(range(n)))
-    assert dflt.pair_items == dflt.nitems > 0          # every item's automaton is a pair automaton
+    assert dflt.pair_items == 0 and dflt.nitems > 0
+    _, two = _prepare([0, 1 << 20], pats, [0] * n, list(range(n)), api.tune(step_bytes=2))
+    assert two.pair_items == two.nitems == dflt.nitems   # every item's automaton is a pair automaton
     _, one = _prepare([0, 1 << 20], pats, [0] * n, list(range(n)), api.tune(step_bytes=1))
     assert one.pair_items == 0 and one.nitems == dflt.nitems
     many = _random_set(rng, 300, 20, 40)
@@ -210,3 +213,18 @@ def test_merged_prepare_pair_automata():
     assert w.pair_items == 0
     rc, _ = _prepare([0, 1000], pats, [0], [0], api.tune(step_bytes=3))
     assert rc == api.DFA_EINVAL
+
+
+def test_merged_prepare_round_bytes():
+    """Rounds of 32 or 64 bytes per walk: the plan records the choice for the run, and the
+    larger rounds' transpose buffers leave less LDS for workgroups with large automata."""
+    rng = np.random.default_rng(9)
+    pats = _random_set(rng, 300, 20, 40)
+    n = len(pats)
+    _, r32 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=32))
+    _, r64 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=64))
+    assert int(r32.reserved[1]) == 32 and int(r64.reserved[1]) == 64
+    assert r32.nitems == r64.nitems and r32.nautomata == r64.nautomata
+    assert r64.lds_bytes - r32.lds_bytes == r64.waves_per_group * 64 * 32
+    _, dflt = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)))
+    assert int(dflt.reserved[1]) in (32, 64)
