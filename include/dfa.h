@@ -144,7 +144,7 @@ int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t *table, in
  *           rate when lanes of a wave meet in the same bank),
  *   mode 1: addresses computed, in 8 chains per thread, from the chain's
  *           previous value as value x row + column (an automaton step's
- *           dependent read),
+ *           dependent read), rows of 61 bytes or of 5 two-byte entries,
  *   mode 2: addresses where lane l of each half-wave reads dword l of a row
  *           (no two lanes of a half-wave in one bank: the conflict-free rate).
  * `sink` (device, 8 bytes, 8-byte aligned) is written only in a case that

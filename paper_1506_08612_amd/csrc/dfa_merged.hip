@@ -97,6 +97,8 @@ struct MAuto {
     uint32_t lut_hi;
     uint32_t key_lo;      // byte h of (key_hi:key_lo): the one byte slot h's lut entry holds
     uint32_t key_hi;
+    int32_t scaled;       // one-step entries are byte offsets of the next state's row (else state numbers)
+    uint32_t magic;       // ceil(2^32 / row bytes): a row offset's state number is its high product
 };
 
 struct MItem {
@@ -139,6 +141,9 @@ struct MCtx {
     int64_t fin_base;
     uint32_t cs, lut_lo, lut_hi, key_lo, key_hi;  // register classes (MAuto)
     uint32_t wts0, wts1;  // pair automata: byte weights (ncls, 1) of each pair of a text word
+    // one-step table entries: e = q qrow, a row at byte e qscale (qrow qscale = row2),
+    // the first reporting entry Fx = F qrow
+    uint32_t qrow, qscale, Fx, magic;
 };
 
 // Pair automata: the byte map sits at LDS 0 and the pair table at kPairMaps,
@@ -166,9 +171,11 @@ __device__ __forceinline__ bool reg_classes(uint32_t w, const MCtx &x, uint32_t 
     return __builtin_amdgcn_perm(x.key_hi, x.key_lo, h) == w;
 }
 
-// The classes of the four bytes of w, byte b of the result for byte b of w:
-// from registers, else from the LDS maps (pair automata: the byte map of c at
-// 0; one-step automata: the 16-bit map of 2 c, their table being at 0).
+// The class bytes of the four bytes of w, byte b of the result for byte b of
+// w: from registers, else from the LDS maps.  Pair automata: c (the byte map
+// at 0).  One-step automata: 2 c, the byte offset of the class's column (the
+// 16-bit map at cmap; their table is at 0 and has at most 128 classes where
+// this is called).
 template <bool PAIR>
 __device__ __forceinline__ uint32_t word_classes(uint32_t w, const MCtx &x) {
     uint32_t P;
@@ -178,17 +185,24 @@ __device__ __forceinline__ uint32_t word_classes(uint32_t w, const MCtx &x) {
         for (int b = 0; b < 4; ++b) {
             const uint32_t byte = (w >> (8 * b)) & 0xffu;
             const uint32_t c = PAIR ? uint32_t(*reinterpret_cast<lds_u8c *>(uintptr_t(byte)))
-                                    : uint32_t(*reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * byte))) >> 1;
+                                    : uint32_t(*reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * byte)));
             P |= c << (8 * b);
         }
     }
     return P;
 }
 
-// A reporting state reached at byte j of the overlap: count each reported
-// pattern whose match starts inside the span (j - m + 1 < own).
-__device__ __forceinline__ void overlap_hit(const MParams &p, const MCtx &x, uint32_t q, uint32_t j, uint32_t own) {
-    const int64_t g = x.fin_base + int64_t(q - x.F);
+// Index among the automaton's reporting states of a one-step table entry
+// e >= Fx (a row offset's state number is a high product with the magic
+// reciprocal, exact for offsets below 2^16 that are multiples of row2).
+__device__ __forceinline__ uint32_t fin_index(uint32_t e, const MCtx &x) {
+    return x.qrow == 1u ? e - x.Fx : __umulhi(e - x.Fx, x.magic);
+}
+
+// A reporting state (index f) reached at byte j of the overlap: count each
+// reported pattern whose match starts inside the span (j - m + 1 < own).
+__device__ __forceinline__ void overlap_hit(const MParams &p, const MCtx &x, uint32_t f, uint32_t j, uint32_t own) {
+    const int64_t g = x.fin_base + int64_t(f);
     const int32_t e1 = p.out_off[g + 1];
     for (int32_t e = p.out_off[g]; e < e1; ++e) {
         const OutEntry oe = p.out_ent[e];
@@ -198,7 +212,7 @@ __device__ __forceinline__ void overlap_hit(const MParams &p, const MCtx &x, uin
 
 // Walk 16 bytes one byte per step with the lane's [lo, own, len) deciding
 // (edge waves and every overlap); byte b of word w is byte jb + 4w + b of the
-// walk.  Per half of the unit: its 8 byte classes first (they do not depend
+// walk, q a one-step table entry.  Per half of the unit: its 8 byte classes first (they do not depend
 // on the state, so their reads are in flight together), then the 8 steps,
 // which keep only the transition read on the state chain, then the visits of
 // the states reached (their counter updates off the chain).
@@ -214,28 +228,29 @@ __device__ __forceinline__ void mwalk16_guarded(const v4u &t, uint32_t &q, uint3
                 uintptr_t(x.cmap + 2u * ((t[2 * h + i / 4] >> (8 * (i % 4))) & 0xffu)));
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2[i]));
+            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.qscale) + k2[i]));
             if (jb + uint32_t(8 * h + i) < L.lo) q = 0;  // in front of the segment: stay in the start state
             qs[i] = q;
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const uint32_t j = jb + uint32_t(8 * h + i);
-            if (qs[i] >= x.F) {
+            if (qs[i] >= x.Fx) {
                 if (j < L.own)
-                    atomicAdd(hist + (qs[i] - x.F), 1u);
+                    atomicAdd(hist + fin_index(qs[i], x), 1u);
                 else if (j < L.len)
-                    overlap_hit(p, x, qs[i], j, L.own);
+                    overlap_hit(p, x, fin_index(qs[i], x), j, L.own);
             }
         }
     }
 }
 
-// Walk 16 bytes of a full wave one byte per step (one-step automata).  Per
-// text word: the classes of its bytes, then its 4 steps, which keep only the
-// transition read on the state chain, then one test of the largest state
-// reached against F (reporting states are numbered last) before the visits
-// are counted.
+// Walk 16 bytes of a full wave one byte per step (one-step automata whose
+// entries are row offsets).  Per text word: the column offsets 2 c of its
+// bytes, then its 4 steps, each one add (the row offset plus a byte of the
+// column offsets) and the transition read, then one test of the largest
+// entry reached against Fx (reporting states are numbered last) before the
+// visits are counted.
 __device__ __forceinline__ void mwalk16_full(const v4u &t, uint32_t &q, const MCtx &x, uint32_t *hist) {
 #pragma unroll
     for (int wd = 0; wd < 4; ++wd) {
@@ -243,14 +258,13 @@ __device__ __forceinline__ void mwalk16_full(const v4u &t, uint32_t &q, const MC
         uint32_t qs[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint32_t k2 = ((P << 1) >> (8 * i)) & 0x1feu;  // 2 c of byte i
-            q = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(q, x.row2) + k2));
+            q = *reinterpret_cast<lds_u16 *>(uintptr_t(q + ((P >> (8 * i)) & 0xffu)));
             qs[i] = q;
         }
-        if (max(max(qs[0], qs[1]), max(qs[2], qs[3])) >= x.F) {
+        if (max(max(qs[0], qs[1]), max(qs[2], qs[3])) >= x.Fx) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (qs[i] >= x.F) atomicAdd(hist + (qs[i] - x.F), 1u);
+                if (qs[i] >= x.Fx) atomicAdd(hist + fin_index(qs[i], x), 1u);
         }
     }
 }
@@ -259,10 +273,10 @@ __device__ __forceinline__ void mwalk16_full(const v4u &t, uint32_t &q, const MC
 // byte, or bit 15: after its first) counts its visits; qp is the state before
 // the pair and c1 its first byte.
 __device__ __forceinline__ void pair_visits(uint32_t e, uint32_t qp, uint32_t c1, const MCtx &x, uint32_t *hist) {
-    if (e & kMidReports) {
+    if (e & kMidReports) {  // the one-step table's entry after c1
         const uint32_t k2 = *reinterpret_cast<lds_u16 *>(uintptr_t(x.cmap + 2u * c1));
         const uint32_t mid = *reinterpret_cast<lds_u16 *>(uintptr_t(__umul24(qp, x.row2) + k2));
-        atomicAdd(hist + (mid - x.F), 1u);
+        atomicAdd(hist + fin_index(mid, x), 1u);
     }
     const uint32_t q = e & (kMidReports - 1u);
     if (q >= x.F) atomicAdd(hist + (q - x.F), 1u);
@@ -334,6 +348,7 @@ __device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, i
         fetch_round_or_none<1, LINE>(pb, p.text, wbase, S, lane_off, lane_off, off_none, r + 3, rlast);
         mwalk_round<LINE, PAIR>(xb, lane, q, x, hist);
     }
+    if (PAIR) q *= x.qrow;  // the pair walk's state as a one-step table entry
     const int hu = (maxm - 1 + 15) / 16;
     const uint8_t *ov = p.text + wstart + S;
     v4u halo[H];
@@ -374,12 +389,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kWavesPerSi
     x.cmap = uint32_t(__builtin_amdgcn_readfirstlane(au.cmap_off));
     x.hist = ib;
     x.F = F;
+    const bool scaled = __builtin_amdgcn_readfirstlane(au.scaled) != 0;
+    x.qrow = scaled ? x.row2 : 1u;
+    x.qscale = scaled ? 1u : x.row2;
+    x.Fx = F * x.qrow;
+    x.magic = uint32_t(__builtin_amdgcn_readfirstlane(int(au.magic)));
     x.fin_base = au.fin_base;
     x.cs = uint32_t(__builtin_amdgcn_readfirstlane(au.cls_shift));
     x.lut_lo = uint32_t(__builtin_amdgcn_readfirstlane(int(au.lut_lo)));
     x.lut_hi = uint32_t(__builtin_amdgcn_readfirstlane(int(au.lut_hi)));
     x.key_lo = uint32_t(__builtin_amdgcn_readfirstlane(int(au.key_lo)));
     x.key_hi = uint32_t(__builtin_amdgcn_readfirstlane(int(au.key_hi)));
+    // lut_lo and key_lo kept in vector registers: a v_perm reads one scalar operand
+    asm volatile("v_mov_b32 %0, %1" : "=v"(x.lut_lo) : "s"(x.lut_lo));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(x.key_lo) : "s"(x.key_lo));
     x.wts0 = (2u * ncls) | (2u << 8);
     x.wts1 = (2u * ncls << 16) | (2u << 24);
     const uint32_t stage = (x.hist + 4u * nfin + 15u) & ~15u;
@@ -414,7 +437,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kWavesPerSi
     const uint32_t lane_off = uint32_t(lane / G::U) * uint32_t(S) + 16u * uint32_t(lane % G::U);
     const int rounds_all = int((S + maxm - 1 + LINE - 1) / LINE);
     const int64_t wlast = wbase + int64_t(kWave - 1) * S;
-    const bool full = wbase >= it.seg_lo && wlast + S <= it.own_end && wlast + S + maxm - 1 <= it.seg_end &&
+    // (one-step automata take the full-wave path where their entries are row offsets)
+    const bool full = (PAIR || scaled) && wbase >= it.seg_lo && wlast + S <= it.own_end &&
+                      wlast + S + maxm - 1 <= it.seg_end &&
                       wlast + int64_t(rounds_all) * LINE <= p.n;
 
     if (full) {
@@ -532,11 +557,13 @@ int64_t groups_per_cu(int64_t bytes, int waves, int line) {
     return groups_for(bytes + int64_t(waves) * stage_bytes_per_wave(line), waves);
 }
 
-// Register classes of an automaton (the device side's reg_classes): the
-// first shift s that gives its pattern bytes distinct slots, preferring one
-// where 'N' (an assembly gap, of the default class unless a pattern holds it)
-// gets a slot of its own; else keys that no byte matches.
-void set_reg_classes(const dfa::AcAutomaton &a, MAuto &m) {
+// Register classes of an automaton (the device side's reg_classes), each
+// slot holding factor x its byte's class (2 c, the column's byte offset, for
+// one-step automata; c for pair automata): the first shift s that gives its
+// pattern bytes distinct slots, preferring one where 'N' (an assembly gap, of
+// the default class unless a pattern holds it) gets a slot of its own; else
+// keys that no byte matches.
+void set_reg_classes(const dfa::AcAutomaton &a, int factor, MAuto &m) {
     std::vector<int> pb;
     for (int b = 0; b < 256; ++b)
         if (a.cls[b]) pb.push_back(b);
@@ -561,7 +588,7 @@ void set_reg_classes(const dfa::AcAutomaton &a, MAuto &m) {
         bool used[8] = {};
         for (int b : pb) {
             key[slot(b, shift)] = uint8_t(b);
-            lut[slot(b, shift)] = uint8_t(a.cls[b]);
+            lut[slot(b, shift)] = uint8_t(factor * a.cls[b]);
             used[slot(b, shift)] = true;
         }
         for (int h = 0; h < 8; ++h) {
@@ -604,7 +631,6 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     m.first_final = a.first_final;
     m.ncls = a.ncls;
     m.maxm = maxm;
-    set_reg_classes(a, m);
     m.table_off = int64_t(hp.area.size());
     m.fin_base = int64_t(hp.out_off.size()) - 1;
     const int64_t ns = a.nstates, nc = a.ncls;
@@ -621,13 +647,17 @@ int add_automaton(const std::vector<int64_t> &ks, const int32_t *pair_pat, const
     // ms against 0.45 ms one-step; 72 8-mers over 1 GB, 0.32 against 0.30 ms.
     // Taken only when the plan asks for two bytes per step.
     m.pair = pair_ok && hp.pack_pairs;
+    set_reg_classes(a, m.pair ? 1 : 2, m);
+    // one-step entries as row offsets where they fit 16 bits and 2 c a byte
+    m.scaled = (ns * 2 * nc <= 65536 && nc <= 128) ? 1 : 0;
+    m.magic = uint32_t(((uint64_t(1) << 32) + uint64_t(2 * nc) - 1) / uint64_t(2 * nc));
     const int64_t tab1 = m.pair ? int64_t(kPairMaps) + pairs : 0;  // LDS offset of the one-step table
     m.cmap_off = int32_t(tab1 + one);
     m.image_bytes = int32_t(tab1 + one + kCmapBytes);
     hp.area.resize(hp.area.size() + size_t(m.image_bytes), 0);
     uint8_t *img = hp.area.data() + m.table_off;
     uint16_t *tab = reinterpret_cast<uint16_t *>(img + tab1);
-    for (size_t i = 0; i < a.next.size(); ++i) tab[i] = uint16_t(a.next[i]);
+    for (size_t i = 0; i < a.next.size(); ++i) tab[i] = uint16_t(m.scaled ? a.next[i] * 2 * nc : a.next[i]);
     uint16_t *cm = reinterpret_cast<uint16_t *>(img + m.cmap_off);
     for (int b = 0; b < 256; ++b) cm[b] = uint16_t(tab1 + 2 * a.cls[b]);
     if (m.pair) {
@@ -784,6 +814,8 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         const int64_t pack_budget = pp ? std::min<int64_t>(budget, (65536 - 32 - fixed) / (per_state - 4) *
                                                                        per_state + fixed)
                                        : budget;
+        // one-step entries stay row offsets (16 bits) while the table is at most 64 KiB
+        const int64_t max_states = ncls <= 128 ? 65536 / (2 * ncls) : int64_t(DFA_AC_MAX_STATES);
         const size_t a_first = hp.autos.size();
         std::vector<int64_t> cur;
         int64_t states = 1;
@@ -797,8 +829,8 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
                 while (common < n && patterns[pat_off[j] + common] == patterns[pat_off[jp] + common]) ++common;
             }
             const int64_t add = pat_len[j] - common;
-            if (!cur.empty() &&
-                ((states + add) * per_state + fixed > pack_budget || states + add > DFA_AC_MAX_STATES)) {
+            if (!cur.empty() && ((states + add) * per_state + fixed > pack_budget ||
+                                 states + add > DFA_AC_MAX_STATES || states + add > max_states)) {
                 const int rc = add_automaton(cur, pair_pat, patterns, pat_off, pat_len, hp);
                 if (rc != DFA_OK) return rc;
                 cur.clear();

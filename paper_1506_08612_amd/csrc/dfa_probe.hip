@@ -17,13 +17,17 @@
 //                bank: the conflict-free read rate;
 //   dependent    eight chains per lane, each read's address computed from the
 //                previous value of its chain as an automaton step computes
-//                the next row from the state (value x row + column): the
-//                rate a walk reaches when every lane has eight walks in
-//                flight.
+//                the next row from the state (value x row + column), over
+//                rows of 61 one-byte or of 5 two-byte entries (a class-
+//                compressed automaton's row over A, C, G, T and the rest):
+//                the rate a walk reaches when every lane has eight walks in
+//                flight.  Row strides that are multiples of 128 bytes would
+//                put every lane of a wave in one bank.
 //
-// The table is 16 KiB of values below 128 (a row number), every address is
-// inside it by construction, and the loaded values are kept alive by a store
-// that only an impossible checksum would make.
+// The table is 16 KiB, every address is inside it by construction (values
+// are row numbers: below 128 for the independent reads, below 256 or 1600 for
+// the dependent ones), and the loaded values are kept alive by a store that
+// only an impossible checksum would make.
 
 #include <hip/hip_runtime.h>
 
@@ -40,6 +44,9 @@ constexpr int kProbeThreads = 512;
 constexpr int kReadsPerIter = 8;
 constexpr uint32_t kStride = 1022;   // bytes between a lane's independent reads (even)
 constexpr uint32_t kAdvance = 2474;  // bytes a lane's base moves per iteration (even)
+constexpr uint32_t kRow8 = 61;       // dependent reads: bytes per row of 1-byte entries (256 rows)
+constexpr uint32_t kRow16 = 5;       // ... entries per row of 2-byte entries (1600 rows)
+constexpr uint32_t kRows16 = 1600;
 
 typedef __attribute__((address_space(3))) const uint8_t lds8;
 typedef __attribute__((address_space(3))) const uint16_t lds16;
@@ -64,10 +71,17 @@ enum ProbeMode { kIndependent = 0, kDependent = 1, kLinear = 2 };
 template <int WIDTH, int MODE>
 __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsigned long long *sink) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // values below 128: one byte each, or the low byte of each 16-bit entry
-    const uint32_t keep = WIDTH == 1 ? 0x7f7f7f7fu : 0x007f007fu;
-    for (int i = threadIdx.x; i < kProbeBytes / 4; i += blockDim.x)
-        reinterpret_cast<uint32_t *>(smem)[i] = mix(uint32_t(i) * 2654435761u + 12345u) & keep;
+    if (MODE == kDependent && WIDTH == 2) {
+        // row numbers below 1600 (1600 rows of 5 entries: 16000 bytes)
+        for (int i = threadIdx.x; i < kProbeBytes / 2; i += blockDim.x)
+            reinterpret_cast<uint16_t *>(smem)[i] = uint16_t(mix(uint32_t(i) * 2654435761u + 12345u) % kRows16);
+    } else {
+        // values below 128 (independent reads), or any byte (row numbers of the
+        // 256 one-byte rows of the dependent reads)
+        const uint32_t keep = MODE == kDependent ? 0xffffffffu : WIDTH == 1 ? 0x7f7f7f7fu : 0x007f007fu;
+        for (int i = threadIdx.x; i < kProbeBytes / 4; i += blockDim.x)
+            reinterpret_cast<uint32_t *>(smem)[i] = mix(uint32_t(i) * 2654435761u + 12345u) & keep;
+    }
     __syncthreads();
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
@@ -89,23 +103,24 @@ __global__ __launch_bounds__(kProbeThreads) void k_lds_probe(int64_t iters, unsi
             base = (base + kAdvance) & uint32_t(kProbeBytes / 2 - WIDTH);
         }
     } else {  // kDependent
-        // row = value (< 128) x 128 bytes (1-byte entries) or x 64 entries (2-byte), column < 128 / 64
+        // 1-byte entries: row v < 256 of 61 bytes, column 7c < 61 (address < 15616);
+        // 2-byte entries: row v < 1600 of 5, column c % 5 (address < 16000)
         uint32_t v[kReadsPerIter];
 #pragma unroll
-        for (int c = 0; c < kReadsPerIter; ++c) v[c] = mix(tid * kReadsPerIter + c) & 127u;
+        for (int c = 0; c < kReadsPerIter; ++c) v[c] = mix(tid * kReadsPerIter + c) % (WIDTH == 1 ? 256u : kRows16);
         for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
             for (int c = 0; c < kReadsPerIter; ++c) {
                 if (WIDTH == 1)
-                    v[c] = lds_read<1>(__umul24(v[c], 128u) + uint32_t(13 * c));
+                    v[c] = lds_read<1>(__umul24(v[c], kRow8) + uint32_t(7 * c));
                 else
-                    v[c] = lds_read<2>(2u * (__umul24(v[c], 64u) + uint32_t(7 * c)));
+                    v[c] = lds_read<2>(2u * (__umul24(v[c], kRow16) + uint32_t(c % 5)));
             }
         }
 #pragma unroll
         for (int c = 0; c < kReadsPerIter; ++c) acc += v[c];
     }
-    if (acc == 0xffffffffu) sink[0] = acc;  // never true (values < 128): keeps the reads
+    if (acc == 0xffffffffu) sink[0] = acc;  // never true (sums of eight values < 1600): keeps the reads
 }
 
 template <int WIDTH>

@@ -143,19 +143,9 @@ __device__ __forceinline__ void put_record(const ScanParams &p, int s, uint32_t 
     }
 }
 
-// The start offsets of a lane's matches in one unit (hit mask from
-// walk16_hits, first byte in bit 15; a match ending at byte j starts at
-// j - (m - 1)), in increasing order, into the walk's buffer.
-__device__ __forceinline__ void record_hits(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, const ScanParams &p) {
-    while (hm) {
-        const int b = 31 - __clz(hm);
-        if (w.cnt < uint32_t(kBuffered)) put_record(p, 0, w.cnt, uint16_t(jb + uint32_t(15 - b) - (m - 1)));
-        ++w.cnt;
-        hm ^= 1u << b;
-    }
-}
-
-// The same from a marked walk's mask (walk16_marks: byte i of the unit in bit i).
+// The start offsets of a lane's matches in one unit, in increasing order,
+// into the walk's buffer, from a marked walk's mask (walk16_marks: byte i of
+// the unit in bit i; a match ending at byte j starts at j - (m - 1)).
 __device__ __forceinline__ void record_marks(uint32_t hm, uint32_t jb, uint32_t m, WalkLane &w, const ScanParams &p) {
     while (hm) {
         const int b = __builtin_ctz(hm);

@@ -273,3 +273,15 @@ def test_noalloc_scratch_limit_checked_on_the_host():
     # bad arguments are still EINVAL
     assert api.lib.dfa_count_noalloc(fake, -1, fake, 8, fake, fake, 1, None, None) == api.DFA_EINVAL
     assert api.lib.dfa_count_noalloc(fake, 100, fake, 0, fake, fake, 1, None, None) == api.DFA_EINVAL
+
+
+def test_lds_probe_argument_checks_run_before_launch():
+    fake = 1 << 20
+    L = api.lib
+    ok_args = (2, 1, 16, 4, fake, None)
+    for i, bad in ((0, 3), (1, 3), (1, -1), (2, 0), (2, (1 << 20) + 1), (3, 0), (3, (1 << 24) + 1)):
+        a = list(ok_args)
+        a[i] = bad
+        assert L.dfa_lds_probe(*a) == api.DFA_EINVAL, (i, bad)
+    assert L.dfa_lds_probe(2, 1, 16, 4, None, None) == api.DFA_EINVAL
+    assert L.dfa_lds_probe(2, 1, 16, 4, fake + 4, None) == api.DFA_EINVAL  # sink not 8-byte aligned
