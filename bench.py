@@ -496,7 +496,7 @@ def bench_segmented(torch, api, synth):
             "hbm_frac": round(int(w.seg_off[-1]) / ms / 1e6 / HBM_PEAK_GBS, 4),
             "pattern_bytes_per_s": round(pb / (ms * 1e-3), 1), "items": int(b.plan.nitems),
             "pair_items": int(b.plan.pair_items),
-            "method": "merged automata per segment (pair automata where they keep occupancy), HIP graph replay",
+            "method": "merged automata per segment (one byte per step, class bytes from registers), HIP graph replay",
             "separate_automata_ms": round(sep_ms, 3), "counts_equal_separate_automata": equal,
             "cpu_baseline": cpu}
 

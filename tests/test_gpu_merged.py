@@ -241,3 +241,22 @@ def test_register_class_alphabets(alphabet, step, line):
     pp_ = [j for _ in range(2) for j in range(len(pats))]
     got = check(text, seg_off, pats, ps_, pp_, t)
     say(alphabet, "step", step, "line", line, "matches", int(got.sum()))
+
+
+def test_wide_alphabet_automata():
+    """Automata with more than 128 byte classes keep state numbers in their tables and walk
+    every wave on the guarded path; a long pattern of distinct bytes planted in random text,
+    next to a DNA pattern set in another segment."""
+    rng = np.random.default_rng(31)
+    n = 2_000_003
+    text = rng.integers(0, 256, n, dtype=np.uint8)
+    wide = [bytes(range(1, 141)), bytes(range(96, 256)), bytes(range(255, 90, -1))]
+    for p in wide:
+        for at in rng.integers(0, n - 300, 40):
+            text[at:at + len(p)] = np.frombuffer(p, np.uint8)
+    dna = text.copy()
+    dna[1_000_000:] = rng.choice(np.frombuffer(b"ACGT", np.uint8), n - 1_000_000)
+    pats = wide + [dna[1_500_000:1_500_012].tobytes(), b"ACGTACG", b"A"]
+    seg_off = [0, 1_000_000, n]
+    got = check(dna, seg_off, pats, [0, 0, 0, 1, 1, 1, 0], [0, 1, 2, 3, 4, 5, 5])
+    assert got[0] > 0 and got[1] > 0 and got[3] > 0
