@@ -311,14 +311,17 @@ def bench_degenerate(torch, api, d, n):
                                        f"threads, {cpu_s:.1f} s on {cpu_model()}"}}
 
 
-def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0, line_bytes=0, automaton_bytes=0):
+def bench_merged_kernels(torch, api, synth, reps=3, step_bytes=0, line_bytes=0, automaton_bytes=0, chain_bytes=0,
+                         waves=0):
     """The merged scans alone, for kernel traces and shader counters: the 1 GB x 1024-pattern
     plan, the 18 degenerate queries over the same text and the 2000-segment plan, each run
     `reps` times after one warm-up run, with the library's default plan (step_bytes: 1 or 2
     forces one- or two-byte automaton steps; line_bytes: bytes per round; automaton_bytes: the LDS
-    budget of one merged automaton; 0: the library's choice)."""
-    t = (api.tune(step_bytes=step_bytes, line_bytes=line_bytes, automaton_bytes=automaton_bytes)
-         if step_bytes or line_bytes or automaton_bytes else None)
+    budget of one merged automaton; chain_bytes: bytes per walk; waves: waves per workgroup; 0:
+    the library's choice)."""
+    t = (api.tune(step_bytes=step_bytes, line_bytes=line_bytes, automaton_bytes=automaton_bytes,
+                  chain_bytes=chain_bytes, waves_per_group=waves)
+         if step_bytes or line_bytes or automaton_bytes or chain_bytes or waves else None)
     from paper_1506_08612_amd import graph
     out = {}
     w = synth.many_patterns()
@@ -550,6 +553,10 @@ def main(argv=None) -> int:
                     help="--only merged: bytes per automaton step (0: the library's choice)")
     ap.add_argument("--merged-line", type=int, default=0, choices=(0, 32, 64),
                     help="--only merged: bytes per round (0: the library's choice)")
+    ap.add_argument("--merged-chain-bytes", type=int, default=0,
+                    help="--only merged: bytes per walk (a multiple of 128; 0: the library's choice)")
+    ap.add_argument("--merged-waves", type=int, default=0,
+                    help="--only merged: waves per workgroup (0: the library's choice)")
     ap.add_argument("--merged-automaton-bytes", type=int, default=0,
                     help="--only merged: LDS budget of one merged automaton (0: the library's choice)")
     ap.add_argument("--no-study", action="store_true",
@@ -580,7 +587,8 @@ def main(argv=None) -> int:
                 "lds": lambda: bench_lds(torch, api),
                 "merged": lambda: bench_merged_kernels(torch, api, synth, step_bytes=a.merged_step,
                                                         line_bytes=a.merged_line,
-                                                        automaton_bytes=a.merged_automaton_bytes)}
+                                                        automaton_bytes=a.merged_automaton_bytes,
+                                                        chain_bytes=a.merged_chain_bytes, waves=a.merged_waves)}
         print(json.dumps({a.only: legs[a.only]()}), flush=True)
         return 0
     stream = torch.cuda.current_stream()

@@ -39,11 +39,11 @@ BATCH_CANDIDATES: List[Dict[str, int]] = [
 ]
 
 MERGED_CANDIDATES: List[Dict[str, int]] = [
-    dict(),  # library default (80 KiB automata, 8 waves, the plan's round size)
+    dict(),  # library default (64 KiB automata; the plan's round size and waves per workgroup)
     dict(automaton_bytes=48 * 1024),
-    dict(automaton_bytes=64 * 1024, line_bytes=64),
+    dict(automaton_bytes=80 * 1024),
     dict(automaton_bytes=24 * 1024, line_bytes=64),
-    dict(automaton_bytes=80 * 1024, waves_per_group=8, chain_bytes=512),
+    dict(automaton_bytes=64 * 1024, waves_per_group=8),
 ]
 
 _lock = threading.Lock()

@@ -68,8 +68,12 @@ constexpr int kWavesPerSimd = 8;                 // register budget of the scan 
 constexpr int kXcds = 8;                         // workgroups are dealt to the XCDs in turn
 constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 128)
 constexpr int64_t kMaxSpan = 1024;
-constexpr int kDefaultWaves = 8;
-constexpr int kDefaultAutomatonBytes = 80 * 1024;
+constexpr int kMaxWaves = 16;                    // waves per workgroup (the kernel's launch bound)
+// LDS budget of one merged automaton: with 16-wave workgroups and 32-byte
+// rounds, two workgroups of 64 KiB automata fit a CU (1 GB x 1024 patterns:
+// 7 automata, 1.86 ms; 56 KiB: 8, 2.19 ms; 80 KiB: 6 at one workgroup of 16
+// or two of 8 waves, 2.35 ms)
+constexpr int kDefaultAutomatonBytes = 64 * 1024;
 constexpr int kMinAutomatonBytes = 4 * 1024;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kCmapBytes = 512;                  // 256 x u16: twice the class of each byte
@@ -406,7 +410,8 @@ __device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, i
 // in launches of their own, so that each kernel keeps only its own path's
 // registers).  LINE: bytes of every walk staged per round (32 or 64).
 template <int H, bool PAIR, int LINE, bool NT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd))) void k_merged(MParams p) {
+__global__ __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd))) void k_merged(
+    MParams p) {
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     const MItem it = p.items[blockIdx.x];
@@ -556,7 +561,7 @@ struct MHostPlan {
     std::vector<int32_t> out_off{0};
     std::vector<OutEntry> out_ent;
     std::vector<uint8_t> area;  // tables and class maps
-    int waves = kDefaultWaves;
+    int waves = 0;  // waves per workgroup (0: the plan chooses)
     int line = 0;  // bytes of every walk staged per round (0: the plan chooses)
     bool nt = false;  // whole-line non-temporal fetches (64-byte rounds, no tile shared by automata)
     int H = 1;
@@ -784,8 +789,8 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         if (t->line_bytes) hp.line = t->line_bytes;
         if (t->step_bytes == 1) hp.allow_pair = false;
         if (t->step_bytes == 2) hp.pack_pairs = true;
-        if (t->waves_per_group < 0 || t->waves_per_group > 8) {
-            dfa::set_error("tune.waves_per_group=%d outside [1, 8]", t->waves_per_group);
+        if (t->waves_per_group < 0 || t->waves_per_group > kMaxWaves) {
+            dfa::set_error("tune.waves_per_group=%d outside [1, %d]", t->waves_per_group, kMaxWaves);
             return DFA_EINVAL;
         }
         if (t->chain_bytes < 0 || t->chain_bytes % 128 || t->chain_bytes > (1 << 20)) {
@@ -894,20 +899,36 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
     hp.H = maxm_all <= 17 ? 1 : 4;
     int64_t auto_max = 0;
     for (const MAuto &a : hp.autos) auto_max = std::max(auto_max, auto_lds_bytes(a));
-    if (!hp.line) {
-        // 64-byte rounds (whole halves of a line per load: the faster reads)
-        // unless 32-byte rounds, whose transpose buffers take half the LDS,
-        // fit more workgroups per CU, weighting each automaton by the bytes it
-        // walks (1 GB x 1024 patterns in 48 KiB automata: 2.5 ms with 32-byte
-        // rounds and 3 workgroups per CU against 3.3 ms with 64 and 2)
-        double occ[2] = {0, 0};
-        for (size_t oi = 0; oi < order.size(); ++oi) {
-            const double len = double(seg_off[order[oi] + 1] - seg_off[order[oi]]);
-            for (size_t a = seg_autos[oi].first; a < seg_autos[oi].second; ++a)
-                for (int l = 0; l < 2; ++l)
-                    occ[l] += len * double(groups_per_cu(auto_lds_bytes(hp.autos[a]), hp.waves, 32 << l));
-        }
-        hp.line = occ[0] > occ[1] ? 32 : 64;
+    if (!hp.line || !hp.waves) {
+        // The scan is bound by the latency of its dependent table reads, so the
+        // shape is chosen for resident waves per CU, weighting each automaton
+        // by the bytes it walks: 64-byte rounds (whole halves of a line per
+        // load: the faster reads) unless 32-byte rounds, whose transpose
+        // buffers take half the LDS, fit more; 8 waves per workgroup unless 16,
+        // which share one copy of the automaton among twice the waves, fit
+        // more.  (1 GB x 1024 patterns in 48 KiB automata: 2.5 ms with 32-byte
+        // rounds and 3 workgroups of 8 waves per CU against 3.3 ms with 64 and
+        // 2.)
+        double best = -1;
+        int best_line = 64, best_waves = 8;
+        for (int line : {64, 32})
+            for (int waves : {8, 16}) {
+                if ((hp.line && line != hp.line) || (hp.waves && waves != hp.waves)) continue;
+                if (auto_max + int64_t(waves) * stage_bytes_per_wave(line) > kLdsPerCu) continue;
+                double occ = 0;
+                for (size_t oi = 0; oi < order.size(); ++oi) {
+                    const double len = double(seg_off[order[oi] + 1] - seg_off[order[oi]]);
+                    for (size_t a = seg_autos[oi].first; a < seg_autos[oi].second; ++a)
+                        occ += len * double(waves * groups_per_cu(auto_lds_bytes(hp.autos[a]), waves, line));
+                }
+                if (occ > best) {
+                    best = occ;
+                    best_line = line;
+                    best_waves = waves;
+                }
+            }
+        if (!hp.line) hp.line = best_line;
+        if (!hp.waves) hp.waves = best_waves;
     }
     // whole-line non-temporal fetches where every segment has one automaton:
     // 2000 segments 0.426 -> 0.410 ms, 72 8-mers over 1 GB 0.286 -> 0.282 ms
@@ -1095,7 +1116,7 @@ extern "C" int dfa_merged_run(const uint8_t *text, int64_t n, void *workspace, c
         grouped += plan->group_items[g];
     }
     if ((H != 1 && H != 4) || (line != 32 && line != 64) || (nt != 0 && nt != 1) || (nt && line != 64) ||
-        plan->waves_per_group < 1 || plan->waves_per_group > 8 || plan->lds_bytes < 0 ||
+        plan->waves_per_group < 1 || plan->waves_per_group > kMaxWaves || plan->lds_bytes < 0 ||
         plan->lds_bytes > kLdsPerCu || !groups_ok || grouped != plan->nitems) {
         dfa::set_error("dfa_merged_run: plan not made by dfa_merged_prepare");
         return DFA_EINVAL;

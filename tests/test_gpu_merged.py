@@ -61,6 +61,8 @@ def test_one_text_all_lengths():
     dict(waves_per_group=2), dict(waves_per_group=8), dict(chain_bytes=128), dict(chain_bytes=2048),
     dict(chain_bytes=256, waves_per_group=3, automaton_bytes=8192),
     dict(line_bytes=32), dict(line_bytes=64), dict(line_bytes=32, step_bytes=2),
+    dict(waves_per_group=16), dict(waves_per_group=16, line_bytes=64, chain_bytes=128),
+    dict(waves_per_group=16, automaton_bytes=8192, line_bytes=32),
     dict(line_bytes=64, step_bytes=2, chain_bytes=128, waves_per_group=1),
 ])
 def test_launch_shapes(tune):

@@ -105,7 +105,7 @@ def test_merged_prepare_argument_checks():
         ([0, 1000, 500], pats, [0], [0], None),                 # decreasing offsets
         ([0, 1000], pats, [0], [0], api.tune(chain_bytes=192)),  # span not a multiple of 128
         ([0, 1000], pats, [0], [0], api.tune(automaton_bytes=1000)),
-        ([0, 1000], pats, [0], [0], api.tune(waves_per_group=9)),
+        ([0, 1000], pats, [0], [0], api.tune(waves_per_group=17)),
         ([0, 1000], pats, [0], [0], api.tune(line_bytes=128)),    # rounds of 32 or 64 bytes only
         ([0, 1000], [b""], [0], [0], None),                     # empty pattern
         ([0, 1000], [b"A" * 256], [0], [0], None),              # too long
@@ -221,10 +221,29 @@ def test_merged_prepare_round_bytes():
     rng = np.random.default_rng(9)
     pats = _random_set(rng, 300, 20, 40)
     n = len(pats)
-    _, r32 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=32))
-    _, r64 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=64))
+    _, r32 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=32, waves_per_group=8))
+    _, r64 = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)), api.tune(line_bytes=64, waves_per_group=8))
     assert int(r32.reserved[1]) == 32 and int(r64.reserved[1]) == 64
     assert r32.nitems == r64.nitems and r32.nautomata == r64.nautomata
     assert r64.lds_bytes - r32.lds_bytes == r64.waves_per_group * 64 * 32
     _, dflt = _prepare([0, 1 << 24], pats, [0] * n, list(range(n)))
     assert int(dflt.reserved[1]) in (32, 64)
+
+
+def test_merged_prepare_waves_per_workgroup():
+    """16-wave workgroups where they hold more resident waves (one copy of a large automaton
+    shared by twice the waves), 8 where small automata fit four workgroups per CU anyway; a
+    tile holds waves x 64 walks; more than 16 waves is refused."""
+    rng = np.random.default_rng(12)
+    big = _random_set(rng, 1024, 4, 64)
+    n = len(big)
+    _, p16 = _prepare([0, 1 << 26], big, [0] * n, list(range(n)))
+    assert p16.waves_per_group == 16 and p16.nautomata > 1
+    _, p8 = _prepare([0, 1 << 26], big, [0] * n, list(range(n)), api.tune(waves_per_group=8))
+    assert p8.waves_per_group == 8 and p8.nautomata == p16.nautomata
+    assert p8.nitems == 2 * p16.nitems
+    small = _random_set(rng, 6, 6, 12)
+    _, ps = _prepare([0, 1 << 26], small, [0] * 6, list(range(6)))
+    assert ps.waves_per_group == 8
+    rc, _ = _prepare([0, 1000], small, [0], [0], api.tune(waves_per_group=17))
+    assert rc == api.DFA_EINVAL
