@@ -428,9 +428,17 @@ __device__ __forceinline__ void walk_wave(const ScanParams &p, v4u *xb, int lane
 
 }
 
+// Workgroups of up to 16 waves for the default shape (one walk per lane,
+// 64-byte rounds: at most 80 registers, so 16 waves fit a CU), 8 for the
+// others (whose larger register files would not).
+template <int K, int LINE>
+constexpr int scan_max_waves() {
+    return (K == 1 && LINE == 64) ? 16 : 8;
+}
+
 template <int K, int LINE, int MODE, int H>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<K, LINE, MODE>())))
-void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.walk_buf to its wave
+__global__ __launch_bounds__((scan_max_waves<K, LINE>() * kWave))
+    __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<K, LINE, MODE>()))) void k_scan(ScanParams p) {  // by value: the per-walk counting pass moves p.walk_buf to its wave
     using G = Geo<LINE>;
     extern __shared__ __align__(16) unsigned char smem[];
     // measurement hook: the workgroup's start (constant-rate wall clock) and cycles
@@ -1088,16 +1096,17 @@ bool check_tune(const dfa_tune *t) {
         dfa::set_error("tune.chain_bytes=%lld above 2^24", (long long)t->chain_bytes);
         return false;
     }
-    if (t->waves_per_group < 0 || t->waves_per_group > 8) {
-        dfa::set_error("tune.waves_per_group=%d outside [1, 8]", t->waves_per_group);
-        return false;
-    }
     if (t->line_bytes != 0 && t->line_bytes != 64 && t->line_bytes != 128) {
         dfa::set_error("tune.line_bytes=%d must be 64 or 128 (or 0)", t->line_bytes);
         return false;
     }
     const int line = t->line_bytes ? t->line_bytes : kDefaultLine;
     const int K = t->chains_per_lane ? t->chains_per_lane : kDefaultK;
+    const int max_waves = (K == 1 && line == 64) ? 16 : 8;
+    if (t->waves_per_group < 0 || t->waves_per_group > max_waves) {
+        dfa::set_error("tune.waves_per_group=%d outside [1, %d] for this shape", t->waves_per_group, max_waves);
+        return false;
+    }
     if (t->chains_per_lane < 0 || !pick_scan(K, line, kCount, 1)) {
         dfa::set_error("tune: chains_per_lane=%d with line_bytes=%d is not a built shape "
                        "(1 with 64 or 128, 2 with 64)", t->chains_per_lane, line);
@@ -1171,7 +1180,9 @@ int kernel_vgprs(const void *fn) {
 // one table among more waves, which matters once the table is large (long
 // patterns).  Workgroups of 5 to 7 waves measure slower than both even where
 // they fit more waves (the text a workgroup walks is then not a power-of-two
-// number of bytes long).
+// number of bytes long), and so do 16 (a tune's choice for the default
+// shape): m = 32 in 2 workgroups of 16 waves, 28 resident waves, walked 3.2 GB
+// in 0.68 ms against 0.55 ms in 3 workgroups of 8.
 int default_wpg(const void *fn, int K, int line, int m, int mode) {
     const int regs = kernel_vgprs(fn);
     if (regs <= 0) return kDefaultWpg;
@@ -1196,6 +1207,11 @@ bool make_plan(int64_t n, int m, int mode, const dfa_tune *t, Plan &pl) {
         pl.wpg = fn ? default_wpg(fn, pl.K, pl.line, m, mode) : kDefaultWpg;
     }
     pl.lds = scan_lds_bytes(pl.wpg, pl.K, pl.line, m, mode);
+    if (pl.lds > kLdsPerCu) {
+        dfa::set_error("%d waves per workgroup with m=%d need %zu bytes of LDS (%zu per CU)", pl.wpg, m, pl.lds,
+                       kLdsPerCu);
+        return false;
+    }
     if (t && t->chain_bytes > 0) {
         pl.S = t->chain_bytes;
     } else {
@@ -1224,8 +1240,8 @@ int launch_scan(const Plan &pl, int mode, const ScanParams &sp, hipStream_t st) 
         dfa::set_error("no kernel for K=%d line=%d", pl.K, pl.line);
         return DFA_EINVAL;
     }
-    // allow the largest table (m = 255) with the largest workgroup
-    if (!dfa::allow_lds(fn, int(scan_lds_bytes(8, 1, 128, DFA_MAX_M, kCount)))) return DFA_EHIP;
+    // allow any plan's LDS (make_plan keeps it within a CU's)
+    if (!dfa::allow_lds(fn, int(kLdsPerCu))) return DFA_EHIP;
     void *args[] = {const_cast<ScanParams *>(&sp)};
     if (!hip_ok(hipLaunchKernel(fn, dim3(unsigned(pl.blocks)), dim3(pl.wpg * kWave), args, pl.lds, st),
                 "k_scan launch"))
@@ -1315,7 +1331,7 @@ extern "C" int dfa_count(const uint8_t *text, int64_t n, const uint8_t *table, i
     const bool per_wave = want_pos && per_wave_plan(K, m);
     const int count_mode = !want_pos ? kCount : per_wave ? kCountPerWave : kCountPerWalk;
     Plan pl;
-    if (!make_plan(n, m, count_mode, tune, pl)) return DFA_EHIP;
+    if (!make_plan(n, m, count_mode, tune, pl)) return DFA_EINVAL;
     if (want_pos && pl.S > kMaxPositionsSpan) {
         dfa::set_error("dfa_count: positions need chain_bytes <= %lld", (long long)kMaxPositionsSpan);
         return DFA_EINVAL;
@@ -1487,7 +1503,7 @@ extern "C" int64_t dfa_count_timed(const uint8_t *text, int64_t n, const uint8_t
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, reinterpret_cast<unsigned long long *>(count));
     if (!hip_ok(hipGetLastError(), "k_zero_u64 launch")) return DFA_EHIP;
     Plan pl;
-    if (!make_plan(n, m, kCount, tune, pl)) return DFA_EHIP;
+    if (!make_plan(n, m, kCount, tune, pl)) return DFA_EINVAL;
     ScanParams sp{};
     sp.text = text;
     sp.n = n;

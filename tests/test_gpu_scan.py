@@ -74,6 +74,7 @@ TUNES = [
     dict(chain_bytes=4096), dict(chain_bytes=65536),
     dict(line_bytes=64), dict(line_bytes=128), dict(chains_per_lane=2, line_bytes=64),
     dict(waves_per_group=1), dict(waves_per_group=2, line_bytes=64), dict(waves_per_group=8),
+    dict(waves_per_group=16), dict(waves_per_group=16, chain_bytes=128),
     dict(waves_per_group=3, chain_bytes=2000 // 16 * 16, chains_per_lane=2, line_bytes=64),
 ]
 

@@ -101,6 +101,13 @@ def test_count_argument_checks_run_before_launch():
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
     t = api.tune(line_bytes=96)
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
+    # 16 waves per workgroup: only with one walk per lane and 64-byte rounds
+    for bad in (dict(waves_per_group=17), dict(waves_per_group=16, line_bytes=128),
+                dict(waves_per_group=16, chains_per_lane=2, line_bytes=64)):
+        t = api.tune(**bad)
+        assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL, bad
+    t = api.tune(waves_per_group=16)
+    assert api.lib.dfa_count_workspace_bytes(1 << 20, 8, 1, ctypes.byref(t)) > 0
     t = api.tune()
     t.reserved[1] = 5
     assert L.dfa_count(fake, 10, fake, 8, fake, None, 0, None, 0, ctypes.byref(t), None) == api.DFA_EINVAL
