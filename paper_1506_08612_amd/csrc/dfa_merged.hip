@@ -834,8 +834,17 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return seg_off[a + 1] - seg_off[a] > seg_off[b + 1] - seg_off[b];
     });
+    // Patterns of at most kHotLen bytes first (they match often: on DNA a
+    // 4-mer every 256 bytes), then by bytes so that neighbours share trie
+    // prefixes.  A segment split over several automata then has its frequent
+    // visits in one of them: an automaton's visit counters take one LDS
+    // atomic per byte position where any lane of a wave reports, so hits
+    // spread over every automaton cost each of them nearly one per position.
+    constexpr int32_t kHotLen = 6;
     auto pat_less = [&](int64_t a, int64_t b) {
         const int32_t ja = pair_pat[a], jb = pair_pat[b];
+        const bool ha = pat_len[ja] <= kHotLen, hb = pat_len[jb] <= kHotLen;
+        if (ha != hb) return ha;
         const int32_t n = std::min(pat_len[ja], pat_len[jb]);
         const int c = std::memcmp(patterns + pat_off[ja], patterns + pat_off[jb], size_t(n));
         return c ? c < 0 : pat_len[ja] < pat_len[jb];
@@ -844,7 +853,7 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
     int maxm_all = 1;
     std::vector<std::pair<size_t, size_t>> seg_autos;  // [first, end) automata of order[i]
     for (int32_t s : order) {
-        // this segment's pairs in pattern order, so that neighbours share prefixes
+        // this segment's pairs in that order
         std::vector<int64_t> ks = by_seg[size_t(s)];
         std::stable_sort(ks.begin(), ks.end(), pat_less);
         bool used[256] = {};
