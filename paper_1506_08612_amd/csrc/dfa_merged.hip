@@ -21,15 +21,15 @@
 // an LDS histogram and turned into per-pair counts at the end through the
 // per-state output lists.
 //
-// Pair automata.  Where an automaton has few byte classes (DNA patterns have
-// five: A, C, G, T and everything else) its table over PAIRS of classes, the
-// state after two bytes, takes ncls^2 columns per state; small automata (one
-// segment's patterns, a set of degenerate k-mers) fit LDS that way, and a
-// full wave's rounds then take one dependent table read per two bytes instead
-// of two per byte: the transition reads, whose lanes meet in LDS banks, are
-// the scan's bottleneck.  A pair entry carries one more bit: whether the state
+// Pair automata (on request: tune step_bytes = 2).  Where an automaton has
+// few byte classes (DNA patterns have five: A, C, G, T and everything else)
+// its table over PAIRS of classes, the state after two bytes, takes ncls^2
+// columns per state, and a full wave's rounds then take one dependent table
+// read per two bytes.  A pair entry carries one more bit: whether the state
 // after the first byte reports, so that visits stay exact (the rare pair with
-// one recomputes that state with the one-step table).
+// one recomputes that state with the one-step table).  Their larger images
+// leave room for fewer workgroups per CU, and at the occupancy the one-step
+// walk reaches they measured slower.
 //
 // Ownership.  A walk owns the match starts of its span [w, w + S) and reads
 // max(m) - 1 bytes past it (clipped at the segment end).  A match that ends
@@ -43,10 +43,12 @@
 // boundaries (the first walk of a segment may start before the segment and
 // skips the bytes in front of it), rounds of 32 or 64 bytes of every walk
 // staged through a wave-private LDS transpose (32-byte rounds take half the
-// LDS, so that a workgroup with a large automaton leaves room for another),
-// the overlap read from memory after the rounds.  Items are
-// ordered so that consecutive items on one XCD walk the same tile with
-// different automata, which keeps the tile in that XCD's L2.
+// LDS, so that a workgroup with a large automaton leaves room for another;
+// 64-byte rounds are fetched as whole lines, non-temporal, where no tile is
+// walked by a second automaton), the overlap read from memory after the
+// rounds.  Items are ordered so that consecutive items on one XCD walk the
+// same tile with different automata, whose later reads of it then find it in
+// that XCD's L2 while it holds it.
 
 #include <hip/hip_runtime.h>
 
@@ -70,9 +72,9 @@ constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 12
 constexpr int64_t kMaxSpan = 1024;
 constexpr int kMaxWaves = 16;                    // waves per workgroup (the kernel's launch bound)
 // LDS budget of one merged automaton: with 16-wave workgroups and 32-byte
-// rounds, two workgroups of 64 KiB automata fit a CU (1 GB x 1024 patterns:
-// 7 automata, 1.86 ms; 56 KiB: 8, 2.19 ms; 80 KiB: 6 at one workgroup of 16
-// or two of 8 waves, 2.35 ms)
+// rounds, two workgroups of 64 KiB automata fit a CU (1 GB x 1024 patterns,
+// before short patterns were packed first: 7 automata, 1.86 ms; 56 KiB: 8,
+// 2.19 ms; 80 KiB: 6 at one workgroup of 16 or two of 8 waves, 2.35 ms)
 constexpr int kDefaultAutomatonBytes = 64 * 1024;
 constexpr int kMinAutomatonBytes = 4 * 1024;
 constexpr int kLdsPerCu = 160 * 1024;
@@ -144,7 +146,7 @@ struct MCtx {
     uint32_t F;      // first reporting state
     int64_t fin_base;
     uint32_t cs, lut_lo, lut_hi, key_lo, key_hi;  // register classes (MAuto)
-    uint32_t wts0, wts1;  // pair automata: byte weights (ncls, 1) of each pair of a text word
+    uint32_t wts0, wts1;  // pair automata: byte weights (2 ncls, 2) of each pair of a text word
     // one-step table entries: e = q qrow, a row at byte e qscale (qrow qscale = row2),
     // the first reporting entry Fx = F qrow
     uint32_t qrow, qscale, Fx, magic;
@@ -162,9 +164,10 @@ typedef __attribute__((address_space(3))) const uint8_t lds_u8c;
 // Register classes.  Where an automaton's pattern bytes (those of classes 1
 // and up) are at most eight and differ in three consecutive bits [s, s + 3),
 // those bits of a text byte name its slot, and one v_perm over the 8-byte
-// register table (lut_hi:lut_lo) gives the class c of all four bytes of a word
-// at once; the same v_perm over (key_hi:key_lo) gives the byte each slot
-// stands for.  A word whose four bytes equal their slots' bytes is classed in
+// register table (lut_hi:lut_lo) gives the class bytes of all four bytes of
+// a word at once (2 c, a column's byte offset, for one-step automata; c for
+// pair automata); the same v_perm over (key_hi:key_lo) gives the byte each
+// slot stands for.  A word whose four bytes equal their slots' bytes is classed in
 // registers; any other word (a default-class byte in a slot that stands for
 // another byte) takes the LDS class map.  Slots that no pattern byte takes
 // stand for a default-class byte ('N' where it can), with c = 0.  An
@@ -406,9 +409,12 @@ __device__ __forceinline__ void walk_full(const MParams &p, v4u *xb, int lane, i
     }
 }
 
-// PAIR: every item's automaton is a pair automaton (the plan puts those items
-// in launches of their own, so that each kernel keeps only its own path's
-// registers).  LINE: bytes of every walk staged per round (32 or 64).
+// H: overlap units unrolled (1 where every pattern has at most 17 bytes,
+// else 4; longer overlaps loop).  PAIR: every item's automaton is a pair
+// automaton (the plan puts those items in launches of their own, so that
+// each kernel keeps only its own path's registers).  LINE: bytes of every
+// walk staged per round (32 or 64).  NT: 64-byte rounds fetched as whole
+// lines with non-temporal loads.
 template <int H, bool PAIR, int LINE, bool NT>
 __global__ __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd))) void k_merged(
     MParams p) {
@@ -489,9 +495,9 @@ __global__ __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_
         walk_full<H, PAIR, LINE, NT>(p, xb, lane, wbase, wstart, S, lane_off, maxm, q, x, L, smem);
     } else if (__builtin_amdgcn_ballot_w64(L.own > L.lo) != 0) {
         // edge waves (the segment's first or last walks, or the text's end): one byte per
-        // step; a wave none of whose walks owns a byte (past the segment's end in a tile
-        // sized for 8 waves) has nothing to walk
-        // rounds up to the longest walk of the wave
+        // step, the rounds up to the longest walk of the wave; a wave none of whose walks
+        // owns a byte (past the segment's end in a tile sized for the workgroup's waves)
+        // has nothing to walk
         int need = int((L.len + uint32_t(LINE) - 1u) / uint32_t(LINE));
         for (int o = kWave / 2; o > 0; o >>= 1) need = max(need, __shfl_xor(need, o));
         const int rounds = __builtin_amdgcn_readfirstlane(min(need, rounds_all));
@@ -566,8 +572,9 @@ struct MHostPlan {
     bool nt = false;  // whole-line non-temporal fetches (64-byte rounds, no tile shared by automata)
     int H = 1;
     int lds = 0;  // dynamic LDS of the largest launch
-    // launch groups (pair automata needing at most a third, a half, all of a
-    // CU's LDS per workgroup; then one-step automata): items and LDS of each
+    // launch groups (pair automata, then one-step automata, each by the
+    // workgroups per CU their LDS leaves room for: 4 or more, 3, 2, 1): items
+    // and LDS of each
     int64_t group_items[DFA_MERGED_GROUPS] = {};
     int group_lds[DFA_MERGED_GROUPS] = {};
     int64_t text_bytes = 0;
@@ -580,9 +587,9 @@ struct MHostPlan {
 };
 
 // Pair automata: at most kPairMaxCls byte classes (a state's row of ncls^2
-// entries grows fast; the byte map's 2 c and the weight ncls of a pair's
-// column sum are bytes), states below 2^15, every image offset below 64 KiB
-// (the 16-bit class map holds the one-step table's offset).
+// entries grows fast; the weight 2 ncls of a pair's column sum is a byte),
+// states below 2^15, every image offset below 64 KiB (the 16-bit class map
+// holds the one-step table's offset).
 constexpr int kPairMaxCls = 11;
 
 int64_t auto_lds_bytes(const MAuto &a) {
