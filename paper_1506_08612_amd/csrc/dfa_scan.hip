@@ -286,6 +286,12 @@ constexpr int halo_units_for(int m) { return m <= 17 ? 1 : m <= 33 ? 2 : 4; }
 // to fit 6 waves per SIMD (at most 80 registers): the per-walk counting pass
 // with 4 overlap units would otherwise need 81 (the compiler then keeps one
 // overlap unit in scratch between the first round and the end of the walk).
+// A budget of 64 registers (8 waves per SIMD) for the count-only and
+// count-per-wave walks measured slower where it changed the code: with 2
+// overlap units the compiler keeps the second in scratch, and m = 32 walked
+// 3.2 GB in 0.60 ms against 0.54 ms, in workgroups of 8 or of 16 waves (32
+// resident per CU instead of 24); with 1 unit the count-only walk (64
+// registers instead of 72) took 0.49-0.59 ms against 0.50-0.55.
 template <int K, int LINE, int MODE>
 constexpr int scan_waves_per_eu() {
     return (K == 1 && LINE == 64 && (MODE == kCount || MODE == kCountPerWalk || MODE == kCountPerWave)) ? 6 : 1;
@@ -1178,11 +1184,10 @@ int kernel_vgprs(const void *fn) {
 // each workgroup needs (its transpose buffers plus its own copy of the
 // table).  Smaller workgroups refill a CU at a finer grain; larger ones share
 // one table among more waves, which matters once the table is large (long
-// patterns).  Workgroups of 5 to 7 waves measure slower than both even where
-// they fit more waves (the text a workgroup walks is then not a power-of-two
-// number of bytes long), and so do 16 (a tune's choice for the default
-// shape): m = 32 in 2 workgroups of 16 waves, 28 resident waves, walked 3.2 GB
-// in 0.68 ms against 0.55 ms in 3 workgroups of 8.
+// patterns).  Workgroups of 5 to 7 waves measured slower than both even where
+// they fit more waves (m = 32: 0.59-0.61 ms for 3.2 GB against 0.54 in 4 or
+// 8), and so did 16 (a tune's choice for the default shape) where registers
+// allow only one such workgroup per CU: m = 32, 16 resident waves, 0.68 ms.
 int default_wpg(const void *fn, int K, int line, int m, int mode) {
     const int regs = kernel_vgprs(fn);
     if (regs <= 0) return kDefaultWpg;
