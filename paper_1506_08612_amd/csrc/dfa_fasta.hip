@@ -31,7 +31,12 @@
 // by output address and stores whole aligned 16-byte blocks; the partial
 // blocks at a unit's two ends, shared with the neighbouring units, are
 // stored byte by byte.  C's text loads and block stores are non-temporal:
-// each byte is read or written once.
+// each byte is read or written once.  A round in which no byte below 0x40
+// but '\n' occurs (no header can start in it, no '\r' is dropped: almost
+// every round of a genome) takes a short path in A and C: its line starts
+// come from the newlines alone and carry no header flag, so one ballot of
+// the lanes holding a line start replaces the wave-wide prefix max, and only
+// a header line left open by an earlier round can drop bytes.
 
 #include <hip/hip_runtime.h>
 
@@ -184,6 +189,22 @@ __device__ __forceinline__ uint32_t ne_mask(const Piece &x, uint32_t c) {
     return (lo >> 7) | (hi << 1);  // lo, hi = 0x80 x the masks of bytes 0..7, 8..15
 }
 
+// bit j set iff byte j is below 0x40 (its two top bits clear): '\n', '\r' and
+// '>' are, sequence letters are not.  Same gathering as ne_mask.
+__device__ __forceinline__ uint32_t low_mask(const Piece &x) {
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t t = ~(x.w[q] | (x.w[q] << 1)) & 0x80808080u;
+        const uint32_t wgt = (q & 1) ? 0x80402010u : 0x08040201u;
+        if (q < 2)
+            lo = __builtin_amdgcn_udot4(t, wgt, lo, false);
+        else
+            hi = __builtin_amdgcn_udot4(t, wgt, hi, false);
+    }
+    return (lo >> 7) | (hi << 1);
+}
+
 // the 16 bytes with 'a'..'z' made upper case (four at a time; bytes >= 0x80
 // are left alone, and no byte carries into the next)
 __device__ __forceinline__ void upper_case(const Piece &x, uint32_t (&up)[4]) {
@@ -268,6 +289,31 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
     unit_rounds<false>(raw, u0, u1, [&](const Piece &x, int r) {
         const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
+        carry_nl = lane63(int32_t(nl >> 15)) & 1;
+        if (__builtin_amdgcn_ballot_w64((low_mask(x) & ~nl & x.valid) != 0) == 0) {
+            // No byte of the round is below 0x40 except '\n' (the usual
+            // sequence round): no '\r', no header starts, every present byte
+            // that is not '\n' kept unless its line is an open header.  The
+            // last line start before a lane's piece is the carry unless an
+            // earlier lane of the round has one (never a header).
+            const uint32_t starts = ((nl << 1) | prev) & x.valid;
+            const uint32_t open = starts ? (1u << __builtin_ctz(starts)) - 1u : 0xffffu;
+            const uint32_t elig = x.valid & ~nl;
+            const unsigned long long sb = __builtin_amdgcn_ballot_w64(starts != 0);
+            const bool before = __builtin_amdgcn_mbcnt_hi(uint32_t(sb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(sb), 0u)) != 0u;
+            if (!before && carry == kNone) {
+                pre += __popc(elig & open);
+                kept += __popc(elig & ~open);
+            } else {
+                kept += __popc(elig & ~((!before && (carry & 1)) ? open : 0u));
+            }
+            if (sb) {
+                const int h = 63 - __builtin_clzll(sb);
+                const int32_t ls = 2 * (r * kRound + lane * kPer + 31 - __clz(starts | 1u));
+                carry = __builtin_amdgcn_readlane(ls, h);
+            }
+            return;
+        }
         const Lines L = analyse(x, nl, prev);
         const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
         const int32_t ex = max(from_prev_lane(incl, kNone), carry);
@@ -279,7 +325,6 @@ __global__ __launch_bounds__(kThreads) void k_fasta_summary(const uint8_t *raw, 
         }
         hdr += __popc(L.hs);
         carry = max(carry, lane63(incl));
-        carry_nl = lane63(int32_t(nl >> 15)) & 1;
     });
     pre = uint32_t(lane63(int32_t(wave_incl_sum(pre))));
     kept = uint32_t(lane63(int32_t(wave_incl_sum(kept))));
@@ -436,12 +481,32 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
     unit_rounds<true>(raw, u0, u1, [&](const Piece &x, int r) {
         const uint32_t nl = ~ne_mask(x, kNl) & 0xffffu;
         const uint32_t prev = uint32_t(from_prev_lane(int32_t(nl >> 15), carry_nl));
-        const Lines L = analyse(x, nl, prev);
-        const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
-        const int32_t ex = max(from_prev_lane(incl, kNone), carry);
-        const uint32_t keep = L.elig & ~(L.fill | ((ex & 1) ? L.open : 0u));
+        carry_nl = lane63(int32_t(nl >> 15)) & 1;
+        uint32_t keep, hs;
+        int32_t next_carry;
+        if (__builtin_amdgcn_ballot_w64((low_mask(x) & ~nl & x.valid) != 0) == 0) {
+            // a sequence round, read as in the summary pass
+            const uint32_t starts = ((nl << 1) | prev) & x.valid;
+            const uint32_t open = starts ? (1u << __builtin_ctz(starts)) - 1u : 0xffffu;
+            const unsigned long long sb = __builtin_amdgcn_ballot_w64(starts != 0);
+            const bool before = __builtin_amdgcn_mbcnt_hi(uint32_t(sb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(sb), 0u)) != 0u;
+            keep = x.valid & ~nl & ~((!before && (carry & 1)) ? open : 0u);
+            hs = 0;
+            next_carry = carry;
+            if (sb) {
+                const int h = 63 - __builtin_clzll(sb);
+                next_carry = __builtin_amdgcn_readlane(2 * (r * kRound + lane * kPer + 31 - __clz(starts | 1u)), h);
+            }
+        } else {
+            const Lines L = analyse(x, nl, prev);
+            const int32_t incl = wave_incl_max(last_start(L, r * kRound + lane * kPer));
+            const int32_t ex = max(from_prev_lane(incl, kNone), carry);
+            keep = L.elig & ~(L.fill | ((ex & 1) ? L.open : 0u));
+            hs = L.hs;
+            next_carry = max(carry, lane63(incl));
+        }
         // kept bytes and header starts of the lane, packed (each <= 16, wave sums <= 1024)
-        const uint32_t packed = uint32_t(__popc(keep)) | (uint32_t(__popc(L.hs)) << 16);
+        const uint32_t packed = uint32_t(__popc(keep)) | (uint32_t(__popc(hs)) << 16);
         const uint32_t pin = wave_incl_sum(packed);
         const uint32_t pex = pin - packed;
         const uint32_t tot = uint32_t(lane63(int32_t(pin)));
@@ -457,15 +522,14 @@ __global__ __launch_bounds__(kThreads) void k_fasta_write(const uint8_t *raw, in
             }
         }
         // record starts: the kept bytes before each header start
-        for (uint32_t hm = L.hs, k = 0; hm; hm &= hm - 1u, ++k) {
+        for (uint32_t hm = hs, k = 0; hm; hm &= hm - 1u, ++k) {
             const int j = __builtin_ctz(hm);
             const int64_t h = rec + int64_t(pex >> 16) + k;
             if (h >= 0 && h < rec_cap) rec_start[h] = o + int64_t(pex & 0xffffu) + __popc(keep & ((1u << j) - 1u));
         }
         o += int64_t(tot & 0xffffu);
         rec += int64_t(tot >> 16);
-        carry = max(carry, lane63(incl));
-        carry_nl = lane63(int32_t(nl >> 15)) & 1;
+        carry = next_carry;
         __builtin_amdgcn_wave_barrier();
         // store: the head bytes once they are all staged, then whole 16-byte blocks
         if (!head_done && o >= head_end) {

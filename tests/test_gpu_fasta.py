@@ -136,6 +136,27 @@ def test_unit_round_and_piece_boundaries():
     check(write_fasta([(b"r", body)], 61, rng, lower_frac=1.0))
 
 
+def test_open_headers_in_sequence_rounds():
+    # header lines of letters only, LF line ends: the rounds that hold a header's tail
+    # have no byte below 0x40 but '\n', so they take the sequence-round path with a
+    # header still open.  The header's '\n' lands on every offset around piece, round
+    # and unit borders; a '>' inside a sequence line is kept.
+    rng = np.random.default_rng(33)
+    body = synth.iid_gc41(3 * UNIT, 8).tobytes()
+    raw = bytearray(body[:100] + b"\n")
+    for border in (16, ROUND, UNIT):
+        for d in (-17, -16, -1, 0, 1, 15, 16, 300):
+            target = border * (3 + len(raw) // border) + d   # index of the header's '\n'
+            raw += b">" + b"H" * (target - len(raw) - 1) + b"\n"
+            assert raw[target] == ord("\n")
+            raw += body[:int(rng.integers(1, 2000))] + b"\n"
+    raw += body[:500] + b">" + body[:40] + b"\n" + body[:3000]
+    check(bytes(raw))
+    recs = [(b"Name" + b"x" * int(rng.integers(0, 3000)), synth.iid_gc41(int(rng.integers(0, 5000)), 60 + k).tobytes())
+            for k in range(50)]
+    check(write_fasta(recs, 60, rng, lower_frac=0.5))
+
+
 def test_output_alignments():
     # the kept bytes go to out + k for every k: whole 16-byte blocks in the middle
     # of a unit's output, bytes at its two ends
