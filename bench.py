@@ -3,10 +3,12 @@
 
 Workload (one "step"): a 3.2 GB genome-like ASCII text (GC 41 %, 'N' runs of
 geometric mean length 50 kb covering 5 %), resident in HBM before timing; five
-patterns of length 4, 8, 16, 32 and 64 drawn from the text; for each pattern,
-one after another: build the automaton on the host, upload its table, and run
-dfa_count with sorted positions (count + every match start).  `value` is text
-bytes scanned per second over the timed steps (5 x 3.2e9 bytes per step).
+patterns of length 4, 8, 16, 32 and 64 drawn from the text; the five automata
+built on the host and their tables uploaded, then dfa_count with sorted positions
+(count + every match start) for each pattern, the five calls issued alternately
+on two streams (each call's small placement launches overlap the next call's
+walk).  `value` is text bytes scanned per second over the timed steps (5 x 3.2e9
+bytes per step).
 
 Also reported:
 * roofline -- the step's dominant kernel, its walk over the whole text (the
@@ -625,9 +627,15 @@ def main(argv=None) -> int:
     cnt_bufs = [torch.empty(1, dtype=torch.int64, device=dev) for _ in pats]
     wsb = max(api.count_workspace_bytes(n, len(p), True) for p in pats)
     ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
-
-    # every step builds the five automata on the host and uploads their tables in one
-    # asynchronous copy from pinned memory, then launches the five scans back to back
+    # Every step builds the five automata on the host and uploads their tables in one
+    # asynchronous copy from pinned memory, then launches the five scans.  The timed steps
+    # issue them on two streams (default priority), alternately, each stream with its own
+    # workspace: a call's placement and re-walk launches, which fill few CUs, then overlap
+    # the next call's walk; the step ends when both streams are done.  The second run of the
+    # steps (events around every call and walk) issues the calls one after another on one
+    # stream.
+    streams = (stream, torch.cuda.Stream(device=dev))
+    wss = (ws, torch.empty(max(1, wsb), dtype=torch.uint8, device=dev))
     tab_sizes = [api.table_bytes(len(p)) for p in pats]
     tab_offs = np.concatenate(([0], np.cumsum(tab_sizes)[:-1])).astype(np.int64)
     tab_pinned = torch.empty(int(sum(tab_sizes)), dtype=torch.uint8).pin_memory()
@@ -640,17 +648,21 @@ def main(argv=None) -> int:
         copied.synchronize()  # the previous step's upload has left the pinned buffer
         for i, p in enumerate(pats):
             tab_np[tab_offs[i]:tab_offs[i] + tab_sizes[i]] = api.build_table(p).reshape(-1)
-        tab_dev.copy_(tab_pinned, non_blocking=True)
+        tab_dev.copy_(tab_pinned, non_blocking=True)  # after the previous step's calls on both streams
         copied.record(stream)
+        tabs = [tab_dev[tab_offs[i]:tab_offs[i] + tab_sizes[i]] for i in range(len(pats))]
+        if events is None:
+            streams[1].wait_event(copied)
+            for i, p in enumerate(pats):
+                api.count_async(dtext, tabs[i], len(p), cnt_bufs[i], pos_bufs[i], caps[i], wss[i % 2],
+                                stream=streams[i % 2])
+            stream.wait_stream(streams[1])
+            return
         for i, p in enumerate(pats):
-            tab = tab_dev[tab_offs[i]:tab_offs[i] + tab_sizes[i]]
-            if events is None:
-                api.count_async(dtext, tab, len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws, stream=stream)
-                continue
             e0, e1, w0, w1 = events[i]
             e0.record(stream)
             with api.ScanEvents(w0, w1, stream):
-                api.count_async(dtext, tab, len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws, stream=stream)
+                api.count_async(dtext, tabs[i], len(p), cnt_bufs[i], pos_bufs[i], caps[i], ws, stream=stream)
             e1.record(stream)
 
     for _ in range(a.warmup):
