@@ -10,7 +10,7 @@ comparison against the first final state.
 
 Everything here is brute force over strings -- states are kept as the prefix
 strings themselves -- and meant for small pattern sets only.  Parity of the
-GPU path is judged on per-pattern counts against the window-compare
+GPU path is checked on per-pattern counts against the window-compare
 definition in oracle.c; this module pins the automaton the batched path is
 built from.
 """
