@@ -7,8 +7,10 @@
 * the merged scan over segments that end below, straddle and start past 2^32, every
   (segment, pattern) count against the oracle.
 
-FASTA normalisation keeps its unit and output offsets in 64 bits too; it is checked at
-3.25 GB only (the oracle's line-by-line definition is too slow for 4.6 GB here).
+* FASTA normalisation of a 4.6e9-byte FASTA text (60 bases per line, headers on both sides
+  of 2^32 in the input and in the output): the normalised bytes equal the sequence it was
+  written from and the record starts equal the writer's cuts (the expected output is known by
+  construction; the oracle's line-by-line definition is pinned at smaller sizes).
 """
 from __future__ import annotations
 
@@ -95,3 +97,43 @@ def test_merged_segments_past_4gib(big):
     say("pairs", pair_seg.size, "total", int(want.sum()))
     assert want[(pair_seg == 2) & (pair_pat == len(pats) - 1)].sum() >= 1  # the copy across 2^32
     assert np.array_equal(got, want)
+
+
+def test_fasta_past_4gib():
+    width = 60
+    seq = synth.genome_like(4_560_000_000 // width * width, 43, n_frac=0.02, n_run_mean=5000)
+    lines = seq.reshape(-1, width)
+    nl = lines.shape[0]
+    # header line indices: the first line, lines whose bytes sit around 2^32 in the FASTA
+    # text and in the output, and a few others
+    out_line = B32 // width
+    in_line = B32 // (width + 1)
+    heads = sorted({0, 1000, in_line - 1, in_line, in_line + 1, out_line - 1, out_line, out_line + 2, nl - 1})
+    parts, prev = [], 0
+    for i, h in enumerate(heads):
+        body = np.empty((h - prev, width + 1), np.uint8)
+        body[:, :width] = lines[prev:h]
+        body[:, width] = ord("\n")
+        parts.append(body.reshape(-1))
+        parts.append(np.frombuffer(b">rec%d\n" % i, np.uint8))
+        prev = h
+    body = np.empty((nl - prev, width + 1), np.uint8)
+    body[:, :width] = lines[prev:]
+    body[:, width] = ord("\n")
+    parts.append(body.reshape(-1))
+    raw = np.concatenate(parts)
+    del parts, body
+    say("FASTA bytes", raw.size, "records", len(heads))
+    assert raw.size > B32 and seq.size > B32
+    d = api.to_device(raw)
+    del raw
+    out, rec, kept, nrec = api.fasta_normalize(d, 64)
+    assert kept == seq.size and nrec == len(heads)
+    assert rec.cpu().numpy().tolist() == [h * width for h in heads]
+    # compare in pieces (the output is 4.56e9 bytes)
+    step = 1 << 28
+    for lo in range(0, seq.size, step):
+        hi = min(seq.size, lo + step)
+        assert np.array_equal(out[lo:hi].cpu().numpy(), seq[lo:hi]), lo
+    del d, out
+    torch.cuda.empty_cache()
