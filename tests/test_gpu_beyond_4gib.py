@@ -4,8 +4,8 @@
 
 * the single-pattern scan (count + sorted positions, default launch shape) for patterns
   of 4, 12 and 33 bytes against the oracle's window-compare definition, every position;
-* the merged scan over segments that end below, straddle and start past 2^32, every
-  (segment, pattern) count against the oracle.
+* the merged scan and the batched scan with one automaton per pattern over segments that
+  end below, straddle and start past 2^32, every (segment, pattern) count against the oracle.
 
 * FASTA normalisation of a 4.6e9-byte FASTA text (60 bases per line, headers on both sides
   of 2^32 in the input and in the output): the normalised bytes equal the sequence it was
@@ -97,6 +97,9 @@ def test_merged_segments_past_4gib(big):
     say("pairs", pair_seg.size, "total", int(want.sum()))
     assert want[(pair_seg == 2) & (pair_pat == len(pats) - 1)].sum() >= 1  # the copy across 2^32
     assert np.array_equal(got, want)
+    # the batched scan with one automaton per pattern, on the same pairs
+    got_b = api.count_batch(d, seg_off, api.PatternSet(patterns), pair_seg, pair_pat)
+    assert np.array_equal(got_b, want)
 
 
 def test_fasta_past_4gib():
