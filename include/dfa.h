@@ -51,7 +51,9 @@ extern "C" {
  * "choose for me".  Results never depend on these values, only speed does. */
 typedef struct dfa_tune {
     int64_t chain_bytes;     /* bytes of text one automaton walk owns (multiple of 16) */
-    int32_t waves_per_group; /* 64-lane waves per workgroup, 1..8 (merged scans: 1..16) */
+    int32_t waves_per_group; /* 64-lane waves per workgroup, 1..8 (1..16 for merged scans
+                              * and for the single-pattern scan with one walk per lane
+                              * and 64-byte rounds) */
     int32_t chains_per_lane; /* independent walks interleaved in one lane: 1 (or 2 with
                               * 64-byte rounds) */
     int32_t dfas_per_group;  /* batched scans: automata walked together: 2, 4, 8 or 16 */
