@@ -674,6 +674,9 @@ def main(argv=None) -> int:
         one_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the timed steps' outputs (two streams), kept to be compared with the second run's
+    timed_out = [(int(c.item()), int(pb[:min(c0, pb.numel())].sum().item()))
+                 for c, pb, c0 in zip(cnt_bufs, pos_bufs, counts)]
 
     # the same steps again, each call and each text walk bracketed by events
     lat = [[] for _ in pats]
@@ -694,6 +697,9 @@ def main(argv=None) -> int:
             walk_ms[i].append(w0.elapsed_time(w1))
     got = [int(c.item()) for c in cnt_bufs]
     assert got == counts, (got, counts)
+    second_out = [(int(c.item()), int(pb[:min(c0, pb.numel())].sum().item()))
+                  for c, pb, c0 in zip(cnt_bufs, pos_bufs, counts)]
+    assert timed_out == second_out, (timed_out, second_out)
 
     ms_per_step = wall * 1e3 / a.steps
     text_bytes_per_step = n * len(pats)
