@@ -12,13 +12,16 @@
 // Spans are whole 128-byte lines, so a walk's loads never share a line with
 // another round's.
 //
-// Data movement.  Each round a wave fetches the next 128 bytes of each of its
-// walks with coalesced 16-byte loads (8 lanes read one 128-byte line), writes
-// them to a wave-private LDS buffer, and reads them back transposed so that
-// every lane holds 128 consecutive bytes of its own walk in registers.  The
-// loads for round r+1 are in flight while round r is walked.  HBM traffic is
-// the text once plus the m-1 overlap bytes per walk (fetched as the first
-// ceil((m-1)/16) units of the next span's first line).
+// Data movement.  A wave reads its walks' text as whole 128-byte lines with
+// coalesced 16-byte loads (8 lanes read one line; non-temporal), each line
+// two 64-byte rounds (128-byte rounds as a tune).  A round goes to a
+// wave-private LDS buffer and is read back transposed, so that every lane
+// holds the round's bytes of its own walk in registers; the next lines'
+// loads are in flight while the current rounds are walked.  HBM traffic is
+// the text once: a walk's m-1 overlap bytes are the first bytes of the next
+// walk's span, which each lane copies out of the wave's staged first round and
+// keeps in registers (only the wave's last walk loads them, from the next
+// wave's first line).
 //
 // Automaton step (Sec. III.B).  The (m+1) x 256 byte-indexed table lives in
 // LDS with rows padded to 280 bytes, so the rows of the low, most visited
