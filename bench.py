@@ -14,8 +14,9 @@ Also reported:
 * roofline -- the step's dominant kernel, its walk over the whole text (the
   per-walk counting pass of count + positions), bracketed by HIP events on the
   launch stream (dfa_set_scan_events) in every call of a second run of the
-  same steps right after the timed one (an event between two launches leaves
-  the stream idle for ~10-15 us, so the timed steps carry none); algorithmic
+  same steps right after the timed one, with the calls one after another on
+  one stream (an event between two launches leaves the stream idle for ~10-15
+  us, so the timed steps bracket no call or walk); algorithmic
   bytes = the text read once; the count-only scan is timed beside it;
 * read_reduce_GBps -- a trivial read-reduce over the same device buffer (torch's
   sum of its 8-byte words), the streaming-read rate reached in the same run, and
