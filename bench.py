@@ -5,9 +5,9 @@ Workload (one "step"): a 3.2 GB genome-like ASCII text (GC 41 %, 'N' runs of
 geometric mean length 50 kb covering 5 %), resident in HBM before timing; five
 patterns of length 4, 8, 16, 32 and 64 drawn from the text; the five automata
 built on the host and their tables uploaded, then dfa_count with sorted positions
-(count + every match start) for each pattern, the five calls issued alternately
-on two streams (each call's small placement launches overlap the next call's
-walk).  `value` is text bytes scanned per second over the timed steps (5 x 3.2e9
+(count + every match start) for each pattern, the five calls issued in turn on
+three streams (each call's small placement launches overlap the next calls'
+walks).  `value` is text bytes scanned per second over the timed steps (5 x 3.2e9
 bytes per step).
 
 Also reported:
@@ -630,13 +630,14 @@ def main(argv=None) -> int:
     ws = torch.empty(max(1, wsb), dtype=torch.uint8, device=dev)
     # Every step builds the five automata on the host and uploads their tables in one
     # asynchronous copy from pinned memory, then launches the five scans.  The timed steps
-    # issue them on two streams (default priority), alternately, each stream with its own
-    # workspace: a call's placement and re-walk launches, which fill few CUs, then overlap
-    # the next call's walk; the step ends when both streams are done.  The second run of the
-    # steps (events around every call and walk) issues the calls one after another on one
-    # stream.
-    streams = (stream, torch.cuda.Stream(device=dev))
-    wss = (ws, torch.empty(max(1, wsb), dtype=torch.uint8, device=dev))
+    # issue them on three streams (default priority) in turn, each stream with its own
+    # workspace: a call's placement and re-walk launches, which fill few CUs, and its walk's
+    # last workgroups then overlap the next calls' walks; the step ends when every stream is
+    # done.  The second run of the steps (events around every call and walk) issues the calls
+    # one after another on one stream.
+    nstreams = 3
+    streams = (stream,) + tuple(torch.cuda.Stream(device=dev) for _ in range(nstreams - 1))
+    wss = (ws,) + tuple(torch.empty(max(1, wsb), dtype=torch.uint8, device=dev) for _ in range(nstreams - 1))
     tab_sizes = [api.table_bytes(len(p)) for p in pats]
     tab_offs = np.concatenate(([0], np.cumsum(tab_sizes)[:-1])).astype(np.int64)
     tab_pinned = torch.empty(int(sum(tab_sizes)), dtype=torch.uint8).pin_memory()
@@ -649,15 +650,17 @@ def main(argv=None) -> int:
         copied.synchronize()  # the previous step's upload has left the pinned buffer
         for i, p in enumerate(pats):
             tab_np[tab_offs[i]:tab_offs[i] + tab_sizes[i]] = api.build_table(p).reshape(-1)
-        tab_dev.copy_(tab_pinned, non_blocking=True)  # after the previous step's calls on both streams
+        tab_dev.copy_(tab_pinned, non_blocking=True)  # after the previous step's calls on every stream
         copied.record(stream)
         tabs = [tab_dev[tab_offs[i]:tab_offs[i] + tab_sizes[i]] for i in range(len(pats))]
         if events is None:
-            streams[1].wait_event(copied)
+            for st in streams[1:]:
+                st.wait_event(copied)
             for i, p in enumerate(pats):
-                api.count_async(dtext, tabs[i], len(p), cnt_bufs[i], pos_bufs[i], caps[i], wss[i % 2],
-                                stream=streams[i % 2])
-            stream.wait_stream(streams[1])
+                api.count_async(dtext, tabs[i], len(p), cnt_bufs[i], pos_bufs[i], caps[i], wss[i % nstreams],
+                                stream=streams[i % nstreams])
+            for st in streams[1:]:
+                stream.wait_stream(st)
             return
         for i, p in enumerate(pats):
             e0, e1, w0, w1 = events[i]
@@ -675,7 +678,7 @@ def main(argv=None) -> int:
         one_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # the timed steps' outputs (two streams), kept to be compared with the second run's
+    # the timed steps' outputs (three streams), kept to be compared with the second run's
     timed_out = [(int(c.item()), int(pb[:min(c0, pb.numel())].sum().item()))
                  for c, pb, c0 in zip(cnt_bufs, pos_bufs, counts)]
 
