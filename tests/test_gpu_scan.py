@@ -252,16 +252,16 @@ def test_count_timed_matches_oracle(n, m, chain):
     assert c3 == c and rows3.shape[0] == min(3, nb) and (rows3[:, 2] > 0).all()
 
 
-def test_calls_on_two_streams_with_their_own_workspaces():
-    """dfa_count with positions issued alternately on two streams, each with its own
-    workspace and outputs (the benchmark's step), then joined: every count and position
-    equals the oracle's, for short (per-walk plan) and long (per-wave plan) patterns."""
+def test_calls_on_several_streams_with_their_own_workspaces():
+    """dfa_count with positions issued in turn on three streams, each with its own
+    workspace (the benchmark's step), then joined: every count and position equals the
+    oracle's, for short (per-walk plan) and long (per-wave plan) patterns."""
     text = gc_text(40_000_000, 77, plant=None)
     rng = np.random.default_rng(78)
     pats = [synth.drawn_pattern(text, m, rng)[0] for m in (4, 8, 12, 16, 32, 64)]
     d = api.to_device(text)
     n = text.size
-    streams = (torch.cuda.current_stream(), torch.cuda.Stream())
+    streams = (torch.cuda.current_stream(), torch.cuda.Stream(), torch.cuda.Stream())
     wsb = max(api.count_workspace_bytes(n, len(p), True) for p in pats)
     wss = [torch.empty(wsb, dtype=torch.uint8, device=d.device) for _ in streams]
     want = [oracle.occurrences(text, p) for p in pats]
@@ -271,9 +271,10 @@ def test_calls_on_two_streams_with_their_own_workspaces():
     torch.cuda.synchronize()
     for rep in range(3):
         for i, p in enumerate(pats):
-            s = (i + rep) % 2
+            s = (i + rep) % len(streams)
             api.count_async(d, tabs[i], len(p), cnts[i], poss[i], poss[i].numel(), wss[s], stream=streams[s])
-        streams[0].wait_stream(streams[1])
+        for st in streams[1:]:
+            streams[0].wait_stream(st)
         torch.cuda.synchronize()
         for i, w in enumerate(want):
             assert int(cnts[i].item()) == w.size, (rep, len(pats[i]))
