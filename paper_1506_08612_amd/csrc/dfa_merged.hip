@@ -70,6 +70,11 @@ constexpr int kWavesPerSimd = 8;                 // register budget of the scan 
 constexpr int kXcds = 8;                         // workgroups are dealt to the XCDs in turn
 constexpr int64_t kMinSpan = 256;                // span bounds (multiples of 128)
 constexpr int64_t kMaxSpan = 1024;
+// Longest span of a segment walked by a single automaton: 72 8-mers over 1 GB
+// in 0.267-0.269 ms at 768 bytes against 0.279-0.284 at 1024 (same box); where
+// several automata walk each tile (and read it from L2 after the first),
+// 1024-byte spans measured faster (1 GB x 1024 patterns: 1.83 against 1.90 ms).
+constexpr int64_t kMaxSpanOne = 768;
 constexpr int kMaxWaves = 16;                    // waves per workgroup (the kernel's launch bound)
 // LDS budget of one merged automaton: with 16-wave workgroups and 32-byte
 // rounds, two workgroups of 64 KiB automata fit a CU (1 GB x 1024 patterns,
@@ -959,7 +964,8 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         return DFA_EINVAL;
     }
     // pass 2: work items, (tile, automaton), on the 128-byte grid of the text;
-    // short segments get short spans
+    // short segments get short spans, long ones at most kMaxSpan (kMaxSpanOne
+    // when one automaton walks the segment)
     const int64_t walks_per_tile = int64_t(hp.waves) * kWave;
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const int32_t s = order[oi];
@@ -971,7 +977,7 @@ int plan_merged(const int64_t *seg_off, int32_t nseg, const uint8_t *patterns, c
         int64_t S = fixed_span;
         if (!S) {
             S = dfa::round_up(dfa::ceil_div(len, walks_per_tile), 128);
-            S = std::min(std::max(S, kMinSpan), kMaxSpan);
+            S = std::min(std::max(S, kMinSpan), na > 1 ? kMaxSpan : kMaxSpanOne);
         }
         const int64_t tile = S * walks_per_tile;
         const int64_t ntiles = dfa::ceil_div(len, tile);
